@@ -1,0 +1,178 @@
+/*
+ * hfqmc.h -- C ABI of the MI355X (gfx950) Hirsch-Fye QMC impurity engine.
+ *
+ * What it solves.  Real-space DMFT for the trapped Hubbard model (Bluemer &
+ * Gorelik, arXiv:1006.2716, Eq. (1)) maps the lattice, through the local
+ * self-energy assumption stated after Eq. (2), onto one Anderson impurity
+ * problem per inequivalent site.  Each impurity is given by its Weiss function
+ * G0_sigma(tau) and is solved with the Hirsch-Fye QMC algorithm that the
+ * paper's "Model and Methods" paragraph names, on L = beta/dtau imaginary-time
+ * slices; the impurity solves are independent, which the paper's parallel
+ * strategy paragraph (after Eq. (2)) exploits by solving all of them at once.
+ * This library runs those solves batched on one GPU.
+ *
+ * Conventions (the paper states none of them; these are the library's):
+ *   - g(tau) = <T c(tau) c^dag(0)> > 0; G[l][l] = g(0+) = 1 - n.
+ *   - Weiss input: L samples g(tau_k), tau_k = k*beta/L, k = 0..L-1, k = 0 is
+ *     tau = 0+.  The L x L matrix is G0[i][j] = g(tau_{i-j}) (i >= j) and
+ *     -g(tau_{i-j+L}) (i < j).  Inputs are expected to be Hartree shifted
+ *     (one-body level includes +U/2), as the HS decoupling requires.
+ *   - lambda: cosh(lambda) = exp(dtau U / 2); V_sigma,l = sigma lambda s_l,
+ *     sigma = +1 (up, index 0), -1 (down, index 1).
+ *   - Metropolis acceptance u < R_up R_dn with u from Philox4x64-10 keyed by
+ *     (seed, site_id); slice l of sweep w uses word (l >> 6) of the block at
+ *     counter (l & 63, w + sweep_offset, 2, 0); u = (x >> 11) 2^-53.  Drawn
+ *     initial fields use the top bit of word (l >> 6) at counter (l & 63, 0, 1, 0)
+ *     (0 -> +1).  Results therefore depend only on the problem, never on the
+ *     batch it runs in.
+ *   - The Dyson equation G = [1 + (1 - G0)(e^V - 1)]^{-1} G0 is solved from
+ *     scratch at the start and after every `recompute_every` sweeps; measured
+ *     sweeps (after n_warmup) contribute g_sigma(tau_k) (k = 0..L, with
+ *     g(tau_L) = n_sigma), n_sigma and d = <n_up n_dn> to n_bins consecutive
+ *     bins (measured sweep m goes to bin floor(m n_bins / n_measure)).
+ *
+ * Memory ownership.  The caller owns every host buffer and ALL device memory:
+ * the workspace of hfqmc_solve and the pool of the site/serving calls are
+ * caller allocations passed as raw device pointers.  The library allocates
+ * only small pinned host staging buffers inside its context.  Inputs are
+ * copied during the call; outputs are written before the call returns (or,
+ * for hfqmc_poll, when it returns HFQMC_OK).
+ *
+ * Errors.  Every call returns an hfqmc_status; no C++ exception crosses the
+ * ABI.  HFQMC_EINVAL: invalid argument, nothing changed.  HFQMC_ENOMEM:
+ * workspace or pool too small.  HFQMC_EDEVICE: a HIP call failed, the context
+ * must be destroyed.  HFQMC_EAGAIN: not admissible now / not finished yet.
+ * HFQMC_ENUMERIC: a non-finite ratio or Green function was seen.
+ * HFQMC_ENOTFOUND: unknown ticket or site.  hfqmc_last_error() describes the
+ * most recent failure on the calling thread.
+ */
+#ifndef HFQMC_H
+#define HFQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HFQMC_OK = 0,
+    HFQMC_EINVAL = -1,
+    HFQMC_ENOMEM = -2,
+    HFQMC_EDEVICE = -3,
+    HFQMC_EAGAIN = -4,
+    HFQMC_ENUMERIC = -5,
+    HFQMC_ENOTFOUND = -6
+} hfqmc_status;
+
+/* FP64: everything in fp64.  MIXED: delayed-update products in fp32 with fp64
+ * accumulation into G; ratios and the Dyson recompute stay fp64. */
+typedef enum { HFQMC_FP64 = 0, HFQMC_MIXED = 1 } hfqmc_precision;
+
+typedef struct hfqmc_ctx hfqmc_ctx;   /* opaque; one per device and stream */
+typedef struct hfqmc_site hfqmc_site; /* opaque device-resident impurity state */
+
+/* One impurity problem.  1 <= L <= 128, beta > 0, U >= 0, n_bins >= 2,
+ * n_measure >= n_bins, recompute_every >= 1, Weiss samples finite with
+ * g(0+) in (0, 1). */
+typedef struct {
+    int32_t L;
+    double beta;
+    double U;
+    const double *weiss[2];     /* host: [0] up, [1] down, L samples each */
+    int64_t n_warmup;
+    int64_t n_measure;
+    int32_t recompute_every;    /* sweeps between from-scratch Dyson solves */
+    int32_t n_bins;
+    uint64_t seed;              /* Philox key word 0 */
+    uint64_t site_id;           /* Philox key word 1 */
+    int64_t sweep_offset;       /* added to the sweep index in the Philox counter */
+    const int8_t *init_fields;  /* host, L entries (+1/-1), or NULL to draw them */
+    int32_t delay;              /* 0: library choice; 1: plain Sherman-Morrison */
+} hfqmc_problem;
+
+/* Result of one impurity.  Pointer members are caller-owned and may be NULL. */
+typedef struct {
+    double *g[2];               /* L+1 bin-averaged g_sigma(tau_k), k = 0..L */
+    double *g_err[2];           /* L+1 errors std(bins)/sqrt(n_bins) */
+    double *bins;               /* n_bins x (2(L+1)+3) bin means:
+                                   g_up[0..L], g_dn[0..L], n_up, n_dn, d */
+    int8_t *final_fields;       /* L entries: fields after the last sweep */
+    double n[2], n_err[2];
+    double docc, docc_err;
+    double accept_rate;
+    double max_drift;           /* max |G_updated - G_from_scratch| seen */
+    int64_t proposals;          /* attempted single-field flips, warm-up included */
+    int64_t accepts;
+    int64_t nonpositive;        /* proposals rejected because R <= 0 */
+    int32_t status;             /* hfqmc_status of this impurity */
+} hfqmc_result;
+
+/* lambda from cosh(lambda) = exp(dtau U / 2) (paper: HF discretisation of
+ * the interval 0 <= tau <= 1/T, "Model and Methods").  EINVAL unless dtau > 0
+ * and U >= 0. */
+hfqmc_status hfqmc_lambda(double dtau, double U, double *lambda_out);
+
+/* Create a context on HIP device `device` that launches on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `tune_cache` may be NULL or a
+ * path to a JSON autotune cache.  *out is owned by the caller until
+ * hfqmc_destroy. */
+hfqmc_status hfqmc_create(int device, void *hip_stream, hfqmc_precision precision, const char *tune_cache,
+                          hfqmc_ctx **out);
+void hfqmc_destroy(hfqmc_ctx *ctx);
+const char *hfqmc_last_error(const hfqmc_ctx *ctx);
+
+/* Bytes of device workspace hfqmc_solve needs for these n problems. */
+hfqmc_status hfqmc_workspace_size(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, size_t *bytes);
+
+/* Solve n independent impurity problems in one batch (blocking).
+ * d_ws: caller-owned device memory of ws_bytes >= hfqmc_workspace_size.
+ * out: n caller-owned results.  Equivalent to stage + run + collect. */
+hfqmc_status hfqmc_solve(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
+                         hfqmc_result *out);
+
+/* Split form of hfqmc_solve.  stage: validate, plan, copy inputs to d_ws
+ * (blocking).  run: enqueue the whole device pass (field initialisation,
+ * Dyson, sweeps, measurement) on the context stream, asynchronous; may be
+ * called repeatedly -- every call recomputes the same deterministic result
+ * from the staged inputs.  collect: wait, copy bins/status back, finalise
+ * results (bin means and errors).  The staged d_ws must stay valid between
+ * the three calls. */
+hfqmc_status hfqmc_stage(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes);
+hfqmc_status hfqmc_run(hfqmc_ctx *ctx);
+hfqmc_status hfqmc_collect(hfqmc_ctx *ctx, hfqmc_result *out);
+
+/* Device time in milliseconds of the sweep kernels of the last hfqmc_run,
+ * from HIP events recorded on the context stream around them. */
+hfqmc_status hfqmc_last_run_ms(hfqmc_ctx *ctx, double *sweep_ms, int32_t *n_launches);
+
+/* ---- device-resident sites (state kept across DMFT iterations) ---- */
+
+/* Give the context caller-owned device memory for site state and serving. */
+hfqmc_status hfqmc_attach_pool(hfqmc_ctx *ctx, void *d_pool, size_t bytes);
+/* Bytes of pool one site of L slices occupies (fields, G, bins, Weiss). */
+hfqmc_status hfqmc_site_bytes(int32_t L, int32_t n_bins, size_t *bytes);
+hfqmc_status hfqmc_site_open(hfqmc_ctx *ctx, int32_t L, int32_t n_bins, hfqmc_site **out);
+hfqmc_status hfqmc_site_close(hfqmc_ctx *ctx, hfqmc_site *site);
+/* Upload the problem (Weiss, U, beta, seeds) without sweeping. */
+hfqmc_status hfqmc_site_define(hfqmc_ctx *ctx, hfqmc_site *site, const hfqmc_problem *problem);
+
+/* Deterministic test hooks (blocking).  set_fields: fields (L x +-1) and a
+ * fresh Dyson solve.  force_flips: flip the listed slices in order, each
+ * accepted unconditionally via Sherman-Morrison; ratios (n, may be NULL)
+ * receive R_up R_dn of each flip.  get_green: G_spin as L x L row-major.
+ * recompute: fresh Dyson solve; *drift (may be NULL) receives
+ * max |G_before - G_after|. */
+hfqmc_status hfqmc_site_set_fields(hfqmc_ctx *ctx, hfqmc_site *site, const int8_t *fields);
+hfqmc_status hfqmc_site_force_flips(hfqmc_ctx *ctx, hfqmc_site *site, const int32_t *slices, int32_t n,
+                                    double *ratios);
+hfqmc_status hfqmc_site_get_green(hfqmc_ctx *ctx, hfqmc_site *site, int32_t spin, double *LxL_row_major);
+hfqmc_status hfqmc_site_get_fields(hfqmc_ctx *ctx, hfqmc_site *site, int8_t *fields);
+hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drift);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFQMC_H */

@@ -1,0 +1,590 @@
+// hfqmc_sweep.hip -- gfx950 kernels of the Hirsch-Fye QMC impurity engine.
+//
+// One workgroup owns one impurity at a time (persistent, work-queue driven).
+// Both spin-resolved L x L Green matrices live in VGPRs as 16 x 16 tiles in
+// the accumulator layout of v_mfma_f64_16x16x4f64 (lane = 16*(row/4) + col,
+// register = row % 4), spread over NW = 2*NT/RT waves: wave w holds RT
+// consecutive tile-rows of one spin.  The method (Hirsch-Fye solver named in
+// the paper's "Model and Methods" paragraph, applied to every inequivalent
+// site of Eq. (1)/(2) in parallel):
+//   ratio   R_s = 1 + (1 - G_s[l][l]) d_s,  d_s = exp(-2 s lambda s_l) - 1
+//   accept  u < R_up R_dn  (Metropolis)
+//   update  G_s += (d_s/R_s) (G_s[:,l] - e_l) G_s[l,:]   (Sherman-Morrison)
+//   Dyson   G = [1 + (1 - G0)(e^V - 1)]^{-1} G0, computed from scratch as L
+//           rank-one updates that switch V_l from 0 to s lambda s_l starting
+//           at G = G0 (the same identity as a flip, with d = exp(V_l) - 1).
+// Decisions need only the diagonal; every wave keeps its own copy of both
+// diagonals distributed over its lanes (slice m in lane m % 64), so a
+// rejected proposal costs no barrier and no LDS traffic.  An accepted one
+// costs one barrier: owners stage column l and row l of G in LDS (double
+// buffered), every lane applies the rank-one update to its tiles.
+#include <hip/hip_runtime.h>
+
+#include "hfqmc_internal.h"
+
+namespace hfqmc {
+
+// ------------------------------------------------------------- Philox4x64-10
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
+// rounds of two 64x64->128 multiplies, Weyl key schedule.
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
+    const uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return U64x4{{c0, c1, c2, c3}};
+}
+
+// Purposes of the Philox counter word 2.
+constexpr uint64_t kPurposeInit = 1, kPurposeSweep = 2;
+
+__device__ __forceinline__ double u01(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+// ------------------------------------------------------------- lane helpers
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <int JW, typename T>
+__device__ __forceinline__ T pick(const T (&a)[JW], int jj) {
+  T r = a[0];
+#pragma unroll
+  for (int k = 1; k < JW; ++k)
+    if (jj == k) r = a[k];
+  return r;
+}
+
+// ------------------------------------------------------------- configuration
+template <int LT_, int RT_>
+struct Cfg {
+  static constexpr int LT = LT_;          // padded slice count (multiple of 16)
+  static constexpr int RT = RT_;          // tile-rows per wave
+  static constexpr int NT = LT / 16;      // tiles per matrix dimension
+  static constexpr int WPS = NT / RT;     // waves per spin
+  static constexpr int NW = 2 * WPS;      // waves per workgroup
+  static constexpr int NTH = 64 * NW;     // threads per workgroup
+  static constexpr int JW = (LT + 63) / 64;  // slices per lane in slice-distributed vectors
+  static constexpr int GS = LT + 1;       // padded LDS row stride of a dumped matrix
+  static constexpr int MINB = LT <= 64 ? 2 : 1;  // workgroups per CU the register budget targets
+  static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
+};
+
+template <class C>
+struct Stage {
+  // Column l of G_s is read from colblk[l/16][i] and row l from
+  // rowq[(l/16)%RT][l%4][j]: owners write every candidate (all tile-columns,
+  // all four rows of a quad) so that no register is ever selected by a
+  // run-time index.
+  double colblk[C::NT][C::LT];
+  double rowq[C::RT][4][C::LT];
+};
+
+template <class C>
+struct Smem {
+  union {
+    Stage<C> stage[2][2];        // [buffer][spin]
+    double dump[C::LT * C::GS];  // one spin's G for the g(tau) estimator
+  } u;
+  double weiss[2][C::LT];        // Weiss samples, zero padded
+  double red[C::NW];
+  int item;
+};
+
+// ------------------------------------------------------------- the engine
+template <class C>
+struct Engine {
+  static constexpr int LT = C::LT, RT = C::RT, NT = C::NT, WPS = C::WPS, JW = C::JW, GS = C::GS;
+
+  Smem<C>& sm;
+  const int tid, wave, lane, spin, wr, q, c;
+  // register state
+  double g[RT][NT][4];  // this wave's tiles of G_spin
+  double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn for slices lane + 64 jj
+  int sv[JW];           // fields for slices lane + 64 jj
+  int buf;              // staging double-buffer selector (uniform)
+  // item constants (uniform)
+  int L;
+  const ImpDesc* d;
+
+  __device__ Engine(Smem<C>& s)
+      : sm(s),
+        tid(threadIdx.x),
+        wave(threadIdx.x >> 6),
+        lane(threadIdx.x & 63),
+        spin((threadIdx.x >> 6) / WPS),
+        wr((threadIdx.x >> 6) % WPS),
+        q((threadIdx.x & 63) >> 4),
+        c(threadIdx.x & 15),
+        buf(0) {}
+
+  __device__ __forceinline__ int row_of(int rt, int r) const { return (wr * RT + rt) * 16 + 4 * q + r; }
+
+  // Rank-one update of both spins for slice l with factors fu = d_up/R_up,
+  // fd = d_dn/R_dn:  G_s += f_s (G_s[:,l] - e_l) G_s[l,:].
+  __device__ void rank1(int l, double fu, double fd) {
+    const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2, rl = l & 3;
+    const int til = l >> 4, rtl = til % RT;
+    Stage<C>& mine = sm.u.stage[buf][spin];
+    if (c == cl) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine.colblk[tj][row_of(rt, r)] = g[rt][tj][r];
+    }
+    if (q == ql && til / RT == wr) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine.rowq[rt][r][tj * 16 + c] = g[rt][tj][r];
+    }
+    __syncthreads();
+    const double f = spin == 0 ? fu : fd;
+    const double* col = mine.colblk[tl];
+    const double* row = mine.rowq[rtl][rl];
+    double a[RT][4], b[NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row_of(rt, r);
+        double x = col[i];
+        if (i == l) x -= 1.0;
+        a[rt][r] = f * x;
+      }
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) b[tj] = row[tj * 16 + c];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[rt][tj][r] = __builtin_fma(a[rt][r], b[tj], g[rt][tj][r]);
+    // the same update applied to this wave's copies of both diagonals
+    const Stage<C>& su = sm.u.stage[buf][0];
+    const Stage<C>& sd = sm.u.stage[buf][1];
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+      const int m = lane + 64 * jj;
+      if (m < LT) {
+        double xu = su.colblk[tl][m], xd = sd.colblk[tl][m];
+        if (m == l) {
+          xu -= 1.0;
+          xd -= 1.0;
+        }
+        dgu[jj] = __builtin_fma(fu * xu, su.rowq[rtl][rl][m], dgu[jj]);
+        dgd[jj] = __builtin_fma(fd * xd, sd.rowq[rtl][rl][m], dgd[jj]);
+      }
+    }
+    buf ^= 1;
+  }
+
+  // Rebuild the diagonal copies from the tiles (after loading saved state).
+  __device__ void diag_from_tiles() {
+    __syncthreads();
+    double* dst = sm.u.stage[0][spin].colblk[0];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row_of(rt, r), j = tj * 16 + c;
+          if (i == j) dst[i] = g[rt][tj][r];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+      const int m = lane + 64 * jj;
+      dgu[jj] = m < LT ? sm.u.stage[0][0].colblk[0][m] : 0.0;
+      dgd[jj] = m < LT ? sm.u.stage[0][1].colblk[0][m] : 0.0;
+    }
+    __syncthreads();
+  }
+
+  // State area: lane-contiguous, lane (wave, lane) owns RT*NT*4 consecutive
+  // doubles, so every element is an immediate offset from one address.
+  __device__ double* state_ptr(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d->off_state) + (size_t)tid * (RT * NT * 4);
+  }
+
+  __device__ void save_tiles(uint8_t* ws) const {
+    double* p = state_ptr(ws);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[(rt * NT + tj) * 4 + r] = g[rt][tj][r];
+  }
+
+  __device__ void load_tiles(uint8_t* ws) {
+    const double* p = state_ptr(ws);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[rt][tj][r] = p[(rt * NT + tj) * 4 + r];
+  }
+
+  // Dyson equation from scratch: G = G0, then switch every slice's potential
+  // from 0 to s*lambda*s_l by a rank-one update.  Returns max |G_old - G_new|
+  // (uniform) when `drift` is set; G_old is parked in the state area.
+  __device__ double recompute(uint8_t* ws, bool drift) {
+    if (drift) save_tiles(ws);
+    // G = G0: each spin's antiperiodic matrix is written to the dump area and
+    // the waves of that spin load their elements from there.
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      __syncthreads();
+      for (int idx = tid; idx < LT * LT; idx += C::NTH) {
+        const int i = idx / LT, j = idx % LT;
+        double v = 0.0;
+        if (i < L && j < L) v = i >= j ? sm.weiss[s][i - j] : -sm.weiss[s][i - j + L];
+        sm.u.dump[i * GS + j] = v;
+      }
+      __syncthreads();
+      if (spin == s) {
+        const double* src = sm.u.dump + row_of(0, 0) * GS + c;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[rt][tj][r] = src[(rt * 16 + r) * GS + tj * 16];
+      }
+    }
+    __syncthreads();
+    {
+      const double g0u = sm.weiss[0][0], g0d = sm.weiss[1][0];
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int m = lane + 64 * jj;
+        dgu[jj] = m < L ? g0u : 0.0;
+        dgd[jj] = m < L ? g0d : 0.0;
+      }
+    }
+    for (int l = 0; l < L; ++l) {
+      const int jj = l >> 6, ln = l & 63;
+      const int s = readlane_i(pick<JW>(sv, jj), ln);
+      const double du = s > 0 ? d->dset_p : d->dset_m;  // up: V_l = +lambda s_l
+      const double dd = s > 0 ? d->dset_m : d->dset_p;  // down: V_l = -lambda s_l
+      const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
+      const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
+      rank1(l, du / Ru, dd / Rd);
+    }
+    double dr = 0.0;
+    if (drift) {
+      const double* p = state_ptr(ws);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - g[rt][tj][r]));
+      dr = wave_max(dr);
+      if (lane == 0) sm.red[wave] = dr;
+      __syncthreads();
+      dr = 0.0;
+      for (int w = 0; w < C::NW; ++w) dr = fmax(dr, sm.red[w]);
+      __syncthreads();
+    }
+    return dr;
+  }
+
+  // g_s(tau_k) sums for this sweep: S_k = sum_l eps G_s[(l+k) mod L][l]; thread
+  // t < L adds S_t / L of spin s into gacc[s].
+  __device__ void measure_green(double (&gacc)[2]) {
+    __syncthreads();  // the dump area aliases the staging buffers
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (spin == s) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.u.dump[row_of(rt, r) * GS + tj * 16 + c] = g[rt][tj][r];
+      }
+      __syncthreads();
+      if (tid < L) {
+        double acc = 0.0;
+        for (int l = 0; l < L; ++l) {
+          const int i = l + tid;
+          acc += i < L ? sm.u.dump[i * GS + l] : -sm.u.dump[(i - L) * GS + l];
+        }
+        gacc[s] += acc / (double)L;
+      }
+      __syncthreads();
+    }
+  }
+
+  __device__ void run(const ImpDesc* desc, uint8_t* ws) {
+    d = desc;
+    L = d->L;
+    const int flags = d->flags;
+    const int NV = n_values(L);
+    double* bins = reinterpret_cast<double*>(ws + d->off_bins);
+    ImpStatus* st = reinterpret_cast<ImpStatus*>(ws + d->off_status);
+    int8_t* fields = reinterpret_cast<int8_t*>(ws + d->off_fields);
+    const double* wv = reinterpret_cast<const double*>(ws + d->off_weiss);
+
+    if (flags & F_ZERO_ACC) {
+      for (int i = tid; i < d->n_bins * NV; i += C::NTH) bins[i] = 0.0;
+      if (tid == 0) {
+        st->proposals = st->accepts = st->nonpositive = st->error = 0;
+        st->max_drift = 0.0;
+      }
+    }
+    for (int i = tid; i < 2 * LT; i += C::NTH) {
+      const int s = i / LT, k = i % LT;
+      sm.weiss[s][k] = k < L ? wv[s * L + k] : 0.0;
+    }
+    // fields
+    if (flags & (F_FIELDS_GIVEN | F_RESUME)) {
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int m = lane + 64 * jj;
+        sv[jj] = m < L ? (fields[m] < 0 ? -1 : 1) : 1;
+      }
+    } else {
+      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d->seed, d->site);
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) sv[jj] = (x.v[jj] >> 63) ? -1 : 1;
+    }
+    __syncthreads();
+    if (flags & F_RESUME) {
+      load_tiles(ws);
+      diag_from_tiles();
+    } else {
+      recompute(ws, false);
+    }
+
+    int64_t proposals = 0, accepts = 0, nonpos = 0;
+    int64_t err = 0;
+    double max_drift = 0.0;
+
+    if (d->op == OP_SWEEPS) {
+      double gacc[2] = {0.0, 0.0};
+      double nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
+      const int64_t nm = d->n_measure, nb = d->n_bins;
+      for (int64_t w = d->sweep_begin; w < d->sweep_end; ++w) {
+        double uv[JW];
+        {
+          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d->rng_offset), kPurposeSweep, 0, d->seed,
+                                        d->site);
+#pragma unroll
+          for (int jj = 0; jj < JW; ++jj) uv[jj] = u01(x.v[jj]);
+        }
+        for (int l = 0; l < L; ++l) {
+          const int jj = l >> 6, ln = l & 63;
+          const int s = readlane_i(pick<JW>(sv, jj), ln);
+          const double du = s > 0 ? d->dflip_p : d->dflip_m;
+          const double dd = s > 0 ? d->dflip_m : d->dflip_p;
+          const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
+          const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
+          const double R = Ru * Rd;
+          const double u = readlane_d(pick<JW>(uv, jj), ln);
+          ++proposals;
+          if (!(R > 0.0)) {  // also catches NaN
+            ++nonpos;
+            if (!(R == R) || R == 0.0) err = 1;
+            continue;
+          }
+          if (u < R) {
+            rank1(l, du / Ru, dd / Rd);
+            if (lane == ln) {
+#pragma unroll
+              for (int k = 0; k < JW; ++k)
+                if (k == jj) sv[k] = -sv[k];
+            }
+            ++accepts;
+          }
+        }
+        const int64_t wl = w;  // request-local sweep index
+        if ((wl + 1) % d->recompute_every == 0) max_drift = fmax(max_drift, recompute(ws, true));
+        if (wl >= d->n_warmup) {
+          const int64_t m = wl - d->n_warmup;
+          const int64_t b = (m * nb) / nm;
+          // density and double occupancy from the diagonals
+          double xu = 0.0, xd = 0.0, xx = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < JW; ++jj) {
+            const int mm = lane + 64 * jj;
+            if (mm < L) {
+              xu += 1.0 - dgu[jj];
+              xd += 1.0 - dgd[jj];
+              xx += (1.0 - dgu[jj]) * (1.0 - dgd[jj]);
+            }
+          }
+          nacc_u += wave_sum(xu) / (double)L;
+          nacc_d += wave_sum(xd) / (double)L;
+          dacc += wave_sum(xx) / (double)L;
+          measure_green(gacc);
+          const bool last = (m + 1 == nm) || (((m + 1) * nb) / nm != b) || (w + 1 == d->sweep_end);
+          if (last) {
+            double* bp = bins + (size_t)b * NV;
+            if (tid < L) {
+              bp[tid] += gacc[0];
+              bp[L + 1 + tid] += gacc[1];
+            }
+            if (tid == 0) {
+              bp[L] += nacc_u;
+              bp[2 * L + 1] += nacc_d;
+              bp[2 * L + 2] += nacc_u;
+              bp[2 * L + 3] += nacc_d;
+              bp[2 * L + 4] += dacc;
+            }
+            gacc[0] = gacc[1] = 0.0;
+            nacc_u = nacc_d = dacc = 0.0;
+          }
+        }
+      }
+    } else if (d->op == OP_FORCE) {
+      const int32_t* slices = reinterpret_cast<const int32_t*>(ws + d->off_force);
+      double* ratios = reinterpret_cast<double*>(ws + d->off_force + 4 * ((d->n_force + 1) & ~1));
+      for (int k = 0; k < d->n_force; ++k) {
+        const int l = slices[k];
+        const int jj = l >> 6, ln = l & 63;
+        const int s = readlane_i(pick<JW>(sv, jj), ln);
+        const double du = s > 0 ? d->dflip_p : d->dflip_m;
+        const double dd = s > 0 ? d->dflip_m : d->dflip_p;
+        const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
+        const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
+        if (tid == 0) ratios[k] = Ru * Rd;
+        rank1(l, du / Ru, dd / Rd);
+        if (lane == ln) {
+#pragma unroll
+          for (int kk = 0; kk < JW; ++kk)
+            if (kk == jj) sv[kk] = -sv[kk];
+        }
+      }
+    } else if (d->op == OP_RECOMPUTE) {
+      max_drift = recompute(ws, true);
+    }
+
+    if (flags & F_SAVE) {
+      save_tiles(ws);
+      if (wave == 0) {
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+          const int m = lane + 64 * jj;
+          if (m < L) fields[m] = (int8_t)sv[jj];
+        }
+      }
+    }
+    if (tid == 0) {
+      st->proposals += proposals;
+      st->accepts += accepts;
+      st->nonpositive += nonpos;
+      st->error |= err;
+      st->max_drift = fmax(st->max_drift, max_drift);
+    }
+    __syncthreads();
+  }
+};
+
+template <class C>
+__global__ __launch_bounds__(C::NTH, C::MINB) void sweep_kernel(const ImpDesc* __restrict__ descs, const int32_t* __restrict__ order,
+                                                       int n_items, int* __restrict__ queue, uint8_t* __restrict__ ws) {
+  __shared__ Smem<C> sm;
+  Engine<C> e(sm);
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = sm.item;
+    __syncthreads();
+    if (it >= n_items) break;
+    e.run(descs + order[it], ws);
+  }
+}
+
+__global__ void zero_kernel(uint64_t* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ------------------------------------------------------------- host dispatch
+struct KernelInfo {
+  int LT, RT, threads;
+  size_t lds;
+  const void* fn;
+};
+
+template <int LT, int RT>
+static KernelInfo info() {
+  using C = Cfg<LT, RT>;
+  return KernelInfo{LT, RT, C::NTH, sizeof(Smem<C>), reinterpret_cast<const void*>(&sweep_kernel<C>)};
+}
+
+static const KernelInfo kKernels[] = {
+    info<16, 1>(), info<32, 1>(), info<48, 1>(), info<64, 1>(), info<64, 2>(), info<80, 1>(),
+    info<96, 1>(), info<96, 2>(), info<112, 1>(), info<128, 1>(), info<128, 2>(),
+};
+
+const KernelInfo* find_kernel(int LT, int RT) {
+  for (const auto& k : kKernels)
+    if (k.LT == LT && k.RT == RT) return &k;
+  return nullptr;
+}
+
+int kernel_threads(const KernelInfo* k) { return k->threads; }
+size_t kernel_lds(const KernelInfo* k) { return k->lds; }
+
+hipError_t kernel_occupancy(const KernelInfo* k, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k->fn, k->threads, 0);
+}
+
+hipError_t launch_sweep(const KernelInfo* k, int grid, hipStream_t st, const ImpDesc* descs, const int32_t* order,
+                        int n_items, int* queue, uint8_t* ws) {
+  void* args[] = {(void*)&descs, (void*)&order, (void*)&n_items, (void*)&queue, (void*)&ws};
+  return hipLaunchKernel(k->fn, dim3(grid), dim3(k->threads), args, 0, st);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 8;
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint64_t*>(p), n);
+  return hipGetLastError();
+}
+
+}  // namespace hfqmc

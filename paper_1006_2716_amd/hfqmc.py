@@ -1,0 +1,310 @@
+"""ctypes binding of libhfqmc.so, the gfx950 Hirsch-Fye QMC engine.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in ``include/hfqmc.h``.  PyTorch provides device
+memory (workspace and pool tensors) and the HIP stream.  There is no CPU
+fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhfqmc.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENUMERIC, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+
+
+class HFQMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hfqmc status {status}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("L", C.c_int32), ("beta", C.c_double), ("U", C.c_double),
+        ("weiss", C.POINTER(C.c_double) * 2),
+        ("n_warmup", C.c_int64), ("n_measure", C.c_int64),
+        ("recompute_every", C.c_int32), ("n_bins", C.c_int32),
+        ("seed", C.c_uint64), ("site_id", C.c_uint64), ("sweep_offset", C.c_int64),
+        ("init_fields", C.POINTER(C.c_int8)), ("delay", C.c_int32),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("g", C.POINTER(C.c_double) * 2), ("g_err", C.POINTER(C.c_double) * 2),
+        ("bins", C.POINTER(C.c_double)), ("final_fields", C.POINTER(C.c_int8)),
+        ("n", C.c_double * 2), ("n_err", C.c_double * 2),
+        ("docc", C.c_double), ("docc_err", C.c_double),
+        ("accept_rate", C.c_double), ("max_drift", C.c_double),
+        ("proposals", C.c_int64), ("accepts", C.c_int64), ("nonpositive", C.c_int64),
+        ("status", C.c_int32),
+    ]
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def lib():
+    """Load libhfqmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "hfqmc_lambda": [C.c_double, C.c_double, C.POINTER(C.c_double)],
+            "hfqmc_create": [C.c_int, _VP, C.c_int, C.c_char_p, C.POINTER(_VP)],
+            "hfqmc_workspace_size": [_VP, C.POINTER(Problem), C.c_int32, C.POINTER(C.c_size_t)],
+            "hfqmc_solve": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t, C.POINTER(Result)],
+            "hfqmc_stage": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t],
+            "hfqmc_run": [_VP],
+            "hfqmc_collect": [_VP, C.POINTER(Result)],
+            "hfqmc_last_run_ms": [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+            "hfqmc_attach_pool": [_VP, _VP, C.c_size_t],
+            "hfqmc_site_bytes": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+            "hfqmc_site_open": [_VP, C.c_int32, C.c_int32, C.POINTER(_VP)],
+            "hfqmc_site_close": [_VP, _VP],
+            "hfqmc_site_define": [_VP, _VP, C.POINTER(Problem)],
+            "hfqmc_site_set_fields": [_VP, _VP, C.POINTER(C.c_int8)],
+            "hfqmc_site_force_flips": [_VP, _VP, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)],
+            "hfqmc_site_get_green": [_VP, _VP, C.c_int32, C.POINTER(C.c_double)],
+            "hfqmc_site_get_fields": [_VP, _VP, C.POINTER(C.c_int8)],
+            "hfqmc_site_recompute": [_VP, _VP, C.POINTER(C.c_double)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.hfqmc_destroy.argtypes = [_VP]
+        L.hfqmc_destroy.restype = None
+        L.hfqmc_last_error.argtypes = [_VP]
+        L.hfqmc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status, what=""):
+    if status != OK:
+        msg = lib().hfqmc_last_error(None)
+        raise HFQMCError(status, f"{what}: {msg.decode() if msg else ''}")
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def lam(dtau: float, U: float) -> float:
+    out = C.c_double()
+    _check(lib().hfqmc_lambda(dtau, U, C.byref(out)), "hfqmc_lambda")
+    return out.value
+
+
+class _Problems:
+    """Marshals problem dicts into an array of Problem structs (keeps buffers alive)."""
+
+    def __init__(self, problems):
+        self.keep = []
+        n = len(problems)
+        self.arr = (Problem * max(n, 1))()
+        for i, p in enumerate(problems):
+            L = int(p["L"])
+            w = np.ascontiguousarray(p["weiss"], dtype=np.float64).reshape(2, L)
+            wu, wd = np.ascontiguousarray(w[0]), np.ascontiguousarray(w[1])
+            init = p.get("init_fields")
+            ia = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
+            self.keep += [wu, wd, ia]
+            pr = self.arr[i]
+            pr.L = L
+            pr.beta = float(p["beta"])
+            pr.U = float(p["U"])
+            pr.weiss[0] = _dp(wu)
+            pr.weiss[1] = _dp(wd)
+            pr.n_warmup = int(p["n_warmup"])
+            pr.n_measure = int(p["n_measure"])
+            pr.recompute_every = int(p.get("recompute_every", 50))
+            pr.n_bins = int(p["n_bins"])
+            pr.seed = int(p["seed"])
+            pr.site_id = int(p.get("site", i))
+            pr.sweep_offset = int(p.get("sweep_offset", 0))
+            pr.init_fields = None if ia is None else ia.ctypes.data_as(C.POINTER(C.c_int8))
+            pr.delay = int(p.get("delay", 0))
+        self.n = n
+
+
+class _Results:
+    def __init__(self, problems):
+        n = len(problems)
+        self.arr = (Result * max(n, 1))()
+        self.bufs = []
+        for i, p in enumerate(problems):
+            L = int(p["L"])
+            g = np.zeros((2, L + 1))
+            ge = np.zeros((2, L + 1))
+            bins = np.zeros((int(p["n_bins"]), 2 * (L + 1) + 3))
+            ff = np.zeros(L, dtype=np.int8)
+            self.bufs.append((g, ge, bins, ff))
+            r = self.arr[i]
+            r.g[0] = g[0].ctypes.data_as(C.POINTER(C.c_double))
+            r.g[1] = g[1].ctypes.data_as(C.POINTER(C.c_double))
+            r.g_err[0] = ge[0].ctypes.data_as(C.POINTER(C.c_double))
+            r.g_err[1] = ge[1].ctypes.data_as(C.POINTER(C.c_double))
+            r.bins = _dp(bins)
+            r.final_fields = ff.ctypes.data_as(C.POINTER(C.c_int8))
+
+    def to_list(self):
+        out = []
+        for i, (g, ge, bins, ff) in enumerate(self.bufs):
+            r = self.arr[i]
+            out.append(dict(g_up=g[0].copy(), g_dn=g[1].copy(), g_up_err=ge[0].copy(), g_dn_err=ge[1].copy(),
+                            bins=bins.copy(), fields=ff.copy(), n_up=r.n[0], n_dn=r.n[1], n_up_err=r.n_err[0],
+                            n_dn_err=r.n_err[1], docc=r.docc, docc_err=r.docc_err, accept_rate=r.accept_rate,
+                            max_drift=r.max_drift, proposals=r.proposals, accepts=r.accepts,
+                            nonpositive=r.nonpositive, status=r.status))
+        return out
+
+
+def _torch():
+    import torch  # noqa: PLC0415  (torch is only needed for device memory and streams)
+    return torch
+
+
+class Context:
+    """A library context bound to a device and a HIP stream (torch's current one by default)."""
+
+    def __init__(self, device: int = 0, stream=None, precision: int = FP64):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = _VP()
+        _check(lib().hfqmc_create(device, _VP(stream.cuda_stream), precision, None, C.byref(h)), "hfqmc_create")
+        self.h = h
+        self._staged = None
+        self._pool = None
+
+    def close(self):
+        if self.h:
+            lib().hfqmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- batch
+    def workspace_size(self, problems) -> int:
+        P = _Problems(problems)
+        b = C.c_size_t()
+        _check(lib().hfqmc_workspace_size(self.h, P.arr, P.n, C.byref(b)), "hfqmc_workspace_size")
+        return b.value
+
+    def alloc_workspace(self, problems):
+        torch = _torch()
+        return torch.empty(self.workspace_size(problems), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def solve(self, problems, workspace=None):
+        self.stage(problems, workspace)
+        self.run()
+        return self.collect()
+
+    def stage(self, problems, workspace=None):
+        if workspace is None:
+            workspace = self.alloc_workspace(problems)
+        P = _Problems(problems)
+        _check(lib().hfqmc_stage(self.h, P.arr, P.n, _VP(workspace.data_ptr()),
+                                 workspace.numel() * workspace.element_size()), "hfqmc_stage")
+        self._staged = (P, list(problems), workspace)
+
+    def run(self):
+        _check(lib().hfqmc_run(self.h), "hfqmc_run")
+
+    def collect(self):
+        P, problems, ws = self._staged
+        R = _Results(problems)
+        st = lib().hfqmc_collect(self.h, R.arr)
+        res = R.to_list()
+        if st not in (OK, ENUMERIC):
+            _check(st, "hfqmc_collect")
+        return res
+
+    def last_run_ms(self):
+        ms = C.c_double()
+        n = C.c_int32()
+        _check(lib().hfqmc_last_run_ms(self.h, C.byref(ms), C.byref(n)), "hfqmc_last_run_ms")
+        return ms.value, n.value
+
+    # ---------------------------------------------------------------- sites
+    def attach_pool(self, nbytes: int):
+        torch = _torch()
+        self._pool = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        _check(lib().hfqmc_attach_pool(self.h, _VP(self._pool.data_ptr()), int(nbytes)), "hfqmc_attach_pool")
+        return self._pool
+
+    def site(self, L: int, n_bins: int = 32):
+        return Site(self, L, n_bins)
+
+
+def site_bytes(L: int, n_bins: int = 32) -> int:
+    b = C.c_size_t()
+    _check(lib().hfqmc_site_bytes(L, n_bins, C.byref(b)), "hfqmc_site_bytes")
+    return b.value
+
+
+class Site:
+    """Device-resident impurity state (fields and Green matrices) in the context pool."""
+
+    def __init__(self, ctx: Context, L: int, n_bins: int = 32):
+        self.ctx = ctx
+        self.L = L
+        h = _VP()
+        _check(lib().hfqmc_site_open(ctx.h, L, n_bins, C.byref(h)), "hfqmc_site_open")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib().hfqmc_site_close(self.ctx.h, self.h), "hfqmc_site_close")
+            self.h = None
+
+    def define(self, problem):
+        P = _Problems([problem])
+        _check(lib().hfqmc_site_define(self.ctx.h, self.h, P.arr), "hfqmc_site_define")
+
+    def set_fields(self, fields):
+        f = np.ascontiguousarray(fields, dtype=np.int8)
+        _check(lib().hfqmc_site_set_fields(self.ctx.h, self.h, f.ctypes.data_as(C.POINTER(C.c_int8))),
+               "hfqmc_site_set_fields")
+
+    def force_flips(self, slices):
+        s = np.ascontiguousarray(slices, dtype=np.int32)
+        ratios = np.zeros(max(len(s), 1))
+        _check(lib().hfqmc_site_force_flips(self.ctx.h, self.h, s.ctypes.data_as(C.POINTER(C.c_int32)), len(s),
+                                            _dp(ratios)), "hfqmc_site_force_flips")
+        return ratios[:len(s)]
+
+    def green(self, spin: int) -> np.ndarray:
+        out = np.zeros((self.L, self.L))
+        _check(lib().hfqmc_site_get_green(self.ctx.h, self.h, spin, _dp(out)), "hfqmc_site_get_green")
+        return out
+
+    def fields(self) -> np.ndarray:
+        out = np.zeros(self.L, dtype=np.int8)
+        _check(lib().hfqmc_site_get_fields(self.ctx.h, self.h, out.ctypes.data_as(C.POINTER(C.c_int8))),
+               "hfqmc_site_get_fields")
+        return out
+
+    def recompute(self) -> float:
+        d = C.c_double()
+        _check(lib().hfqmc_site_recompute(self.ctx.h, self.h, C.byref(d)), "hfqmc_site_recompute")
+        return d.value

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, and its pure-host calls behave."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1006_2716_amd import hfqmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hfqmc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hfqmc_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("hfqmc_lambda", "hfqmc_create", "hfqmc_solve", "hfqmc_workspace_size", "hfqmc_site_force_flips"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(hfqmc.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("dtau,U", [(0.25, 4.0), (0.125, 12.0), (0.2, 8.0), (1.0, 1e-9)])
+def test_lambda_defining_identity(dtau, U):
+    lam = hfqmc.lam(dtau, U)
+    assert np.cosh(lam) == pytest.approx(np.exp(0.5 * dtau * U), rel=1e-14)
+
+
+def test_lambda_rejects_bad_input():
+    with pytest.raises(hfqmc.HFQMCError) as e:
+        hfqmc.lam(0.0, 4.0)
+    assert e.value.status == hfqmc.EINVAL
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.lam(0.25, -1.0)
+
+
+def test_site_bytes_grows_with_L():
+    b16 = hfqmc.site_bytes(16)
+    b64 = hfqmc.site_bytes(64)
+    b128 = hfqmc.site_bytes(128)
+    assert b16 < b64 < b128
+    # the Green tiles dominate: 2 x 128 x 128 doubles
+    assert b128 >= 2 * 128 * 128 * 8
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.site_bytes(129)
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.site_bytes(0)
+
+
+def test_null_context_is_rejected():
+    lib = hfqmc.lib()
+    assert lib.hfqmc_workspace_size(None, None, 0, None) == hfqmc.EINVAL
+    assert lib.hfqmc_run(None) == hfqmc.EINVAL
+    assert lib.hfqmc_collect(None, None) == hfqmc.EINVAL
