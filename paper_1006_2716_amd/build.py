@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     # no packed-fp32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=off", "-Wall", "-Wno-unused-result",
+    # keep branch-selected register reads as branches: sinking them into one
+    # load through a phi of pointers would demote the register tiles to scratch
+    "-mllvm", "-simplifycfg-sink-common=false",
 ]
 
 

@@ -255,6 +255,7 @@ struct hfqmc_ctx {
   std::mutex mu;
   // staged batch
   bool staged = false;
+  bool fields_given = false;
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
   std::vector<hfqmc_problem> probs;
@@ -489,6 +490,8 @@ hfqmc_status hfqmc_stage(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* 
   c->groups = groups;
   c->lo = lo;
   c->host_in.swap(img);
+  c->fields_given = false;
+  for (int i = 0; i < n; ++i) c->fields_given |= p[i].init_fields != nullptr;
   c->staged = true;
   return HFQMC_OK;
 }
@@ -498,9 +501,11 @@ hfqmc_status hfqmc_run(hfqmc_ctx* c) {
   std::lock_guard<std::mutex> g(c->mu);
   if (hfqmc_status s = set_device(c)) return s;
   // fields are inputs when given: restore them (a previous run overwrote them)
-  const size_t fbytes = c->lo.status - c->lo.fields;
-  HIP_TRY(hipMemcpyAsync(c->ws + c->lo.fields, c->host_in.data() + c->lo.fields, fbytes, hipMemcpyHostToDevice,
-                         c->stream));
+  if (c->fields_given) {
+    const size_t fbytes = c->lo.status - c->lo.fields;
+    HIP_TRY(hipMemcpyAsync(c->ws + c->lo.fields, c->host_in.data() + c->lo.fields, fbytes, hipMemcpyHostToDevice,
+                           c->stream));
+  }
   HIP_TRY(launch_zero(c->ws + c->lo.queues, sizeof(int32_t) * 64, c->stream));
   if (hfqmc_status s = ensure_events(c, 2 * c->groups.size())) return s;
   const ImpDesc* descs = reinterpret_cast<const ImpDesc*>(c->ws + c->lo.descs);

@@ -20,9 +20,24 @@
 // buffered), every lane applies the rank-one update to its tiles.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "hfqmc_internal.h"
 
 namespace hfqmc {
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1, so
+// every array index inside f is a constant before any optimisation runs and
+// register arrays can never be demoted to scratch by a run-time index.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // ------------------------------------------------------------- Philox4x64-10
 // Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
@@ -82,9 +97,9 @@ __device__ __forceinline__ double wave_max(double v) {
 template <int JW, typename T>
 __device__ __forceinline__ T pick(const T (&a)[JW], int jj) {
   T r = a[0];
-#pragma unroll
-  for (int k = 1; k < JW; ++k)
-    if (jj == k) r = a[k];
+  static_for<JW>([&](auto k) __attribute__((always_inline)) {
+    if (k > 0 && jj == k) r = a[k];
+  });
   return r;
 }
 
@@ -100,26 +115,24 @@ struct Cfg {
   static constexpr int JW = (LT + 63) / 64;  // slices per lane in slice-distributed vectors
   static constexpr int GS = LT + 1;       // padded LDS row stride of a dumped matrix
   static constexpr int MINB = LT <= 64 ? 2 : 1;  // workgroups per CU the register budget targets
+  static constexpr bool DUMP2 = LT <= 64;        // both spins fit the LDS dump area at once
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
+  static_assert(NTH >= 2 * LT, "measurement needs one thread per (spin, tau_k)");
 };
 
 template <class C>
 struct Stage {
-  // Column l of G_s is read from colblk[l/16][i] and row l from
-  // rowq[(l/16)%RT][l%4][j]: owners write every candidate (all tile-columns,
-  // all four rows of a quad) so that no register is ever selected by a
-  // run-time index.
-  double colblk[C::NT][C::LT];
-  double rowq[C::RT][4][C::LT];
+  double col[C::LT];  // column l of G_s
+  double row[C::LT];  // row l of G_s
 };
 
 template <class C>
 struct Smem {
   union {
-    Stage<C> stage[2][2];        // [buffer][spin]
-    double dump[C::LT * C::GS];  // one spin's G for the g(tau) estimator
+    Stage<C> stage[2][2];                              // [buffer][spin]
+    double dump[(C::DUMP2 ? 2 : 1) * C::LT * C::GS];  // G for the g(tau) estimator
   } u;
-  double weiss[2][C::LT];        // Weiss samples, zero padded
+  double weiss[2][C::LT];  // Weiss samples, zero padded
   double red[C::NW];
   int item;
 };
@@ -132,15 +145,16 @@ struct Engine {
   Smem<C>& sm;
   const int tid, wave, lane, spin, wr, q, c;
   // register state
-  double g[RT][NT][4];  // this wave's tiles of G_spin
+  double g[RT][NT][4];      // this wave's tiles of G_spin
   double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn for slices lane + 64 jj
-  int sv[JW];           // fields for slices lane + 64 jj
-  int buf;              // staging double-buffer selector (uniform)
-  // item constants (uniform)
+  int sv[JW];               // fields for slices lane + 64 jj
+  int buf;                  // staging double-buffer selector (uniform)
+  // item constants (uniform), copied out of memory once per item so that
+  // barriers (memory clobbers) do not force reloads in the hot loop
   int L;
-  const ImpDesc* d;
+  ImpDesc d;
 
-  __device__ Engine(Smem<C>& s)
+  __device__ __forceinline__ Engine(Smem<C>& s)
       : sm(s),
         tid(threadIdx.x),
         wave(threadIdx.x >> 6),
@@ -153,127 +167,107 @@ struct Engine {
 
   __device__ __forceinline__ int row_of(int rt, int r) const { return (wr * RT + rt) * 16 + 4 * q + r; }
 
+  // f(rt, tj, r) over this lane's tile elements, all indices compile-time.
+  template <class F>
+  __device__ __forceinline__ void for_tiles(F&& f) {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) { static_for<NT>([&](auto tj) __attribute__((always_inline)) { static_for<4>([&](auto r) __attribute__((always_inline)) { f(rt, tj, r); }); }); });
+  }
+
   // Rank-one update of both spins for slice l with factors fu = d_up/R_up,
   // fd = d_dn/R_dn:  G_s += f_s (G_s[:,l] - e_l) G_s[l,:].
-  __device__ void rank1(int l, double fu, double fd) {
+  // Column l lives in tile-column l/16 of the lanes with c == l%16; row l in
+  // register l%4 of tile-row l/16 of the lanes with q == (l%16)/4.  Uniform
+  // branches over compile-time indices pick the values to stage, so only the
+  // needed values travel through LDS and no register is indexed at run time.
+  __device__ __forceinline__ void rank1(int l, double fu, double fd) {
     const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2, rl = l & 3;
-    const int til = l >> 4, rtl = til % RT;
+    const int rtl = tl % RT;
     Stage<C>& mine = sm.u.stage[buf][spin];
     if (c == cl) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) mine.colblk[tj][row_of(rt, r)] = g[rt][tj][r];
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        if (tj == tl) static_for<RT>([&](auto rt) __attribute__((always_inline)) { static_for<4>([&](auto r) __attribute__((always_inline)) { mine.col[row_of(rt, r)] = g[rt][tj][r]; }); });
+      });
     }
-    if (q == ql && til / RT == wr) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) mine.rowq[rt][r][tj * 16 + c] = g[rt][tj][r];
+    if (q == ql && tl / RT == wr) {
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        if (rt == rtl)
+          static_for<4>([&](auto r) __attribute__((always_inline)) {
+            if (r == rl) static_for<NT>([&](auto tj) __attribute__((always_inline)) { mine.row[tj * 16 + c] = g[rt][tj][r]; });
+          });
+      });
     }
     __syncthreads();
     const double f = spin == 0 ? fu : fd;
-    const double* col = mine.colblk[tl];
-    const double* row = mine.rowq[rtl][rl];
     double a[RT][4], b[NT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<4>([&](auto r) __attribute__((always_inline)) {
         const int i = row_of(rt, r);
-        double x = col[i];
+        double x = mine.col[i];
         if (i == l) x -= 1.0;
         a[rt][r] = f * x;
-      }
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj) b[tj] = row[tj * 16 + c];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) g[rt][tj][r] = __builtin_fma(a[rt][r], b[tj], g[rt][tj][r]);
+      });
+    });
+    static_for<NT>([&](auto tj) __attribute__((always_inline)) { b[tj] = mine.row[tj * 16 + c]; });
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = __builtin_fma(a[rt][r], b[tj], g[rt][tj][r]); });
     // the same update applied to this wave's copies of both diagonals
     const Stage<C>& su = sm.u.stage[buf][0];
     const Stage<C>& sd = sm.u.stage[buf][1];
-#pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
       if (m < LT) {
-        double xu = su.colblk[tl][m], xd = sd.colblk[tl][m];
+        double xu = su.col[m], xd = sd.col[m];
         if (m == l) {
           xu -= 1.0;
           xd -= 1.0;
         }
-        dgu[jj] = __builtin_fma(fu * xu, su.rowq[rtl][rl][m], dgu[jj]);
-        dgd[jj] = __builtin_fma(fd * xd, sd.rowq[rtl][rl][m], dgd[jj]);
+        dgu[jj] = __builtin_fma(fu * xu, su.row[m], dgu[jj]);
+        dgd[jj] = __builtin_fma(fd * xd, sd.row[m], dgd[jj]);
       }
-    }
+    });
     buf ^= 1;
   }
 
   // Rebuild the diagonal copies from the tiles (after loading saved state).
-  __device__ void diag_from_tiles() {
+  __device__ __forceinline__ void diag_from_tiles() {
     __syncthreads();
-    double* dst = sm.u.stage[0][spin].colblk[0];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = row_of(rt, r), j = tj * 16 + c;
-          if (i == j) dst[i] = g[rt][tj][r];
-        }
+    double* dst = sm.u.stage[0][spin].col;
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      const int i = row_of(rt, r), j = tj * 16 + c;
+      if (i == j) dst[i] = g[rt][tj][r];
+    });
     __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
-      dgu[jj] = m < LT ? sm.u.stage[0][0].colblk[0][m] : 0.0;
-      dgd[jj] = m < LT ? sm.u.stage[0][1].colblk[0][m] : 0.0;
-    }
+      dgu[jj] = m < LT ? sm.u.stage[0][0].col[m] : 0.0;
+      dgd[jj] = m < LT ? sm.u.stage[0][1].col[m] : 0.0;
+    });
     __syncthreads();
   }
 
   // State area: lane-contiguous, lane (wave, lane) owns RT*NT*4 consecutive
   // doubles, so every element is an immediate offset from one address.
-  __device__ double* state_ptr(uint8_t* ws) const {
-    return reinterpret_cast<double*>(ws + d->off_state) + (size_t)tid * (RT * NT * 4);
+  __device__ __forceinline__ double* state_ptr(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + (size_t)tid * (RT * NT * 4);
   }
 
-  __device__ void save_tiles(uint8_t* ws) const {
+  __device__ __forceinline__ void save_tiles(uint8_t* ws) {
     double* p = state_ptr(ws);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p[(rt * NT + tj) * 4 + r] = g[rt][tj][r];
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { p[(rt * NT + tj) * 4 + r] = g[rt][tj][r]; });
   }
 
-  __device__ void load_tiles(uint8_t* ws) {
+  __device__ __forceinline__ void load_tiles(uint8_t* ws) {
     const double* p = state_ptr(ws);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) g[rt][tj][r] = p[(rt * NT + tj) * 4 + r];
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = p[(rt * NT + tj) * 4 + r]; });
   }
 
   // Dyson equation from scratch: G = G0, then switch every slice's potential
   // from 0 to s*lambda*s_l by a rank-one update.  Returns max |G_old - G_new|
   // (uniform) when `drift` is set; G_old is parked in the state area.
-  __device__ double recompute(uint8_t* ws, bool drift) {
+  __device__ __forceinline__ double recompute(uint8_t* ws, bool drift) {
     if (drift) save_tiles(ws);
     // G = G0: each spin's antiperiodic matrix is written to the dump area and
     // the waves of that spin load their elements from there.
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    static_for<2>([&](auto s) __attribute__((always_inline)) {
       __syncthreads();
       for (int idx = tid; idx < LT * LT; idx += C::NTH) {
         const int i = idx / LT, j = idx % LT;
@@ -284,29 +278,23 @@ struct Engine {
       __syncthreads();
       if (spin == s) {
         const double* src = sm.u.dump + row_of(0, 0) * GS + c;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) g[rt][tj][r] = src[(rt * 16 + r) * GS + tj * 16];
+        for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = src[(rt * 16 + r) * GS + tj * 16]; });
       }
-    }
+    });
     __syncthreads();
     {
       const double g0u = sm.weiss[0][0], g0d = sm.weiss[1][0];
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) {
         const int m = lane + 64 * jj;
         dgu[jj] = m < L ? g0u : 0.0;
         dgd[jj] = m < L ? g0d : 0.0;
-      }
+      });
     }
     for (int l = 0; l < L; ++l) {
       const int jj = l >> 6, ln = l & 63;
       const int s = readlane_i(pick<JW>(sv, jj), ln);
-      const double du = s > 0 ? d->dset_p : d->dset_m;  // up: V_l = +lambda s_l
-      const double dd = s > 0 ? d->dset_m : d->dset_p;  // down: V_l = -lambda s_l
+      const double du = s > 0 ? d.dset_p : d.dset_m;  // up: V_l = +lambda s_l
+      const double dd = s > 0 ? d.dset_m : d.dset_p;  // down: V_l = -lambda s_l
       const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
       const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
       rank1(l, du / Ru, dd / Rd);
@@ -314,12 +302,7 @@ struct Engine {
     double dr = 0.0;
     if (drift) {
       const double* p = state_ptr(ws);
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - g[rt][tj][r]));
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - g[rt][tj][r])); });
       dr = wave_max(dr);
       if (lane == 0) sm.red[wave] = dr;
       __syncthreads();
@@ -330,45 +313,78 @@ struct Engine {
     return dr;
   }
 
-  // g_s(tau_k) sums for this sweep: S_k = sum_l eps G_s[(l+k) mod L][l]; thread
-  // t < L adds S_t / L of spin s into gacc[s].
-  __device__ void measure_green(double (&gacc)[2]) {
-    __syncthreads();  // the dump area aliases the staging buffers
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (spin == s) {
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sm.u.dump[row_of(rt, r) * GS + tj * 16 + c] = g[rt][tj][r];
-      }
-      __syncthreads();
-      if (tid < L) {
-        double acc = 0.0;
-        for (int l = 0; l < L; ++l) {
-          const int i = l + tid;
-          acc += i < L ? sm.u.dump[i * GS + l] : -sm.u.dump[(i - L) * GS + l];
-        }
-        gacc[s] += acc / (double)L;
-      }
-      __syncthreads();
+  // g_s(tau_k) sums for this sweep: S_k = sum_l eps G_s[(l+k) mod L][l].
+  // The tiles are dumped to LDS (both spins at once when they fit) and
+  // thread t = s*L + k adds S_k / L of spin s into gacc.
+  __device__ __forceinline__ double diag_sum(const double* m, int k) const {
+    // element ((l+k) mod L, l) sits at k*GS + l*(GS+1), minus L*GS once wrapped
+    constexpr int S = GS + 1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int nw = L - k;  // l < nw: no wrap
+    int l = 0, base = k * GS;
+    for (; l + 4 <= nw; l += 4) {
+      a0 += m[base + l * S];
+      a1 += m[base + (l + 1) * S];
+      a2 += m[base + (l + 2) * S];
+      a3 += m[base + (l + 3) * S];
     }
+    for (; l < nw; ++l) a0 += m[base + l * S];
+    base -= L * GS;
+    for (; l + 4 <= L; l += 4) {
+      a1 -= m[base + l * S];
+      a2 -= m[base + (l + 1) * S];
+      a3 -= m[base + (l + 2) * S];
+      a0 -= m[base + (l + 3) * S];
+    }
+    for (; l < L; ++l) a1 -= m[base + l * S];
+    return (a0 + a1) + (a2 + a3);
   }
 
-  __device__ void run(const ImpDesc* desc, uint8_t* ws) {
-    d = desc;
-    L = d->L;
-    const int flags = d->flags;
+  __device__ __forceinline__ void dump_tiles(double* m) {
+    double* dst = m + row_of(0, 0) * GS + c;
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { dst[(rt * 16 + r) * GS + tj * 16] = g[rt][tj][r]; });
+  }
+
+  __device__ __forceinline__ void measure_green(double& gacc) {
+    __syncthreads();  // the dump area aliases the staging buffers
+    if constexpr (C::DUMP2) {
+      dump_tiles(sm.u.dump + spin * (LT * GS));
+      __syncthreads();
+      if (tid < 2 * L) {
+        const int s = tid >= L, k = tid - s * L;
+        gacc += diag_sum(sm.u.dump + s * (LT * GS), k) / (double)L;
+      }
+    } else {
+      static_for<2>([&](auto s) __attribute__((always_inline)) {
+        if (spin == s) dump_tiles(sm.u.dump);
+        __syncthreads();
+        if (tid >= s * L && tid < (s + 1) * L) gacc += diag_sum(sm.u.dump, tid - s * L) / (double)L;
+        if (s == 0) __syncthreads();
+      });
+    }
+    __syncthreads();  // the next staging write reuses the dump area
+  }
+
+  __device__ __forceinline__ void flip_field(int l) {
+    const int jj = l >> 6, ln = l & 63;
+    if (lane == ln)
+      static_for<JW>([&](auto k) __attribute__((always_inline)) {
+        if (k == jj) sv[k] = -sv[k];
+      });
+  }
+
+  __device__ __forceinline__ void run(const ImpDesc* desc, uint8_t* ws) {
+    d = *desc;
+    L = d.L;
+    const int flags = d.flags;
     const int NV = n_values(L);
-    double* bins = reinterpret_cast<double*>(ws + d->off_bins);
-    ImpStatus* st = reinterpret_cast<ImpStatus*>(ws + d->off_status);
-    int8_t* fields = reinterpret_cast<int8_t*>(ws + d->off_fields);
-    const double* wv = reinterpret_cast<const double*>(ws + d->off_weiss);
+    double* bins = reinterpret_cast<double*>(ws + d.off_bins);
+    ImpStatus* st = reinterpret_cast<ImpStatus*>(ws + d.off_status);
+    int8_t* fields = reinterpret_cast<int8_t*>(ws + d.off_fields);
+    const double* wv = reinterpret_cast<const double*>(ws + d.off_weiss);
 
     if (flags & F_ZERO_ACC) {
-      for (int i = tid; i < d->n_bins * NV; i += C::NTH) bins[i] = 0.0;
+      for (int i = tid; i < d.n_bins * NV; i += C::NTH) bins[i] = 0.0;
       if (tid == 0) {
         st->proposals = st->accepts = st->nonpositive = st->error = 0;
         st->max_drift = 0.0;
@@ -380,15 +396,13 @@ struct Engine {
     }
     // fields
     if (flags & (F_FIELDS_GIVEN | F_RESUME)) {
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) {
         const int m = lane + 64 * jj;
         sv[jj] = m < L ? (fields[m] < 0 ? -1 : 1) : 1;
-      }
+      });
     } else {
-      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d->seed, d->site);
-#pragma unroll
-      for (int jj = 0; jj < JW; ++jj) sv[jj] = (x.v[jj] >> 63) ? -1 : 1;
+      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d.seed, d.site);
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) { sv[jj] = (x.v[jj] >> 63) ? -1 : 1; });
     }
     __syncthreads();
     if (flags & F_RESUME) {
@@ -402,70 +416,84 @@ struct Engine {
     int64_t err = 0;
     double max_drift = 0.0;
 
-    if (d->op == OP_SWEEPS) {
-      double gacc[2] = {0.0, 0.0};
+    if (d.op == OP_SWEEPS) {
+      double gacc = 0.0;  // thread t < 2L: running bin sum of g_s(tau_k), s = t / L, k = t % L
       double nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
-      const int64_t nm = d->n_measure, nb = d->n_bins;
-      for (int64_t w = d->sweep_begin; w < d->sweep_end; ++w) {
+      const int64_t nm = d.n_measure, nb = d.n_bins;
+      for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
         double uv[JW];
         {
-          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d->rng_offset), kPurposeSweep, 0, d->seed,
-                                        d->site);
-#pragma unroll
-          for (int jj = 0; jj < JW; ++jj) uv[jj] = u01(x.v[jj]);
+          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep, 0, d.seed,
+                                        d.site);
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) { uv[jj] = u01(x.v[jj]); });
         }
-        for (int l = 0; l < L; ++l) {
+        // Rejections leave G unchanged, so the decisions of all remaining
+        // slices can be taken at once against the current diagonals: lane m
+        // tests slice m (u_m < R_m, the same arithmetic as a sequential scan)
+        // and the first accepted slice is found with a wave ballot.  Only
+        // accepted flips pay for an update.
+        int l0 = 0;
+        for (;;) {
+          uint64_t acc_mask[JW], bad_mask[JW];
+          double fu_v[JW], fd_v[JW];
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+            const int m = lane + 64 * jj;
+            const bool live = m >= l0 && m < L;
+            const double du = sv[jj] > 0 ? d.dflip_p : d.dflip_m;
+            const double dd = sv[jj] > 0 ? d.dflip_m : d.dflip_p;
+            const double Ru = __builtin_fma(1.0 - dgu[jj], du, 1.0), Rd = __builtin_fma(1.0 - dgd[jj], dd, 1.0);
+            const double R = Ru * Rd;
+            acc_mask[jj] = __ballot(live && uv[jj] < R);
+            bad_mask[jj] = __ballot(live && !(R > 0.0));
+            if (__ballot(live && !(R == R))) err = 1;  // non-finite ratio
+            fu_v[jj] = du / Ru;
+            fd_v[jj] = dd / Rd;
+          });
+          int l = L;
+          static_for<JW>([&](auto k) __attribute__((always_inline)) {
+            constexpr int jj = JW - 1 - decltype(k)::value;  // highest word first, lowest wins
+            if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
+          });
+          // slices [l0, l] were proposed; those with R <= 0 were rejected
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+            const int hi = l - 64 * jj;
+            const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
+            nonpos += __builtin_popcountll(bad_mask[jj] & below);
+          });
+          if (l >= L) {
+            proposals += L - l0;
+            break;
+          }
+          proposals += l - l0 + 1;
           const int jj = l >> 6, ln = l & 63;
-          const int s = readlane_i(pick<JW>(sv, jj), ln);
-          const double du = s > 0 ? d->dflip_p : d->dflip_m;
-          const double dd = s > 0 ? d->dflip_m : d->dflip_p;
-          const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
-          const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
-          const double R = Ru * Rd;
-          const double u = readlane_d(pick<JW>(uv, jj), ln);
-          ++proposals;
-          if (!(R > 0.0)) {  // also catches NaN
-            ++nonpos;
-            if (!(R == R) || R == 0.0) err = 1;
-            continue;
-          }
-          if (u < R) {
-            rank1(l, du / Ru, dd / Rd);
-            if (lane == ln) {
-#pragma unroll
-              for (int k = 0; k < JW; ++k)
-                if (k == jj) sv[k] = -sv[k];
-            }
-            ++accepts;
-          }
+          rank1(l, readlane_d(pick<JW>(fu_v, jj), ln), readlane_d(pick<JW>(fd_v, jj), ln));
+          flip_field(l);
+          ++accepts;
+          l0 = l + 1;
         }
         const int64_t wl = w;  // request-local sweep index
-        if ((wl + 1) % d->recompute_every == 0) max_drift = fmax(max_drift, recompute(ws, true));
-        if (wl >= d->n_warmup) {
-          const int64_t m = wl - d->n_warmup;
+        if ((wl + 1) % d.recompute_every == 0) max_drift = fmax(max_drift, recompute(ws, true));
+        if (wl >= d.n_warmup) {
+          const int64_t m = wl - d.n_warmup;
           const int64_t b = (m * nb) / nm;
           // density and double occupancy from the diagonals
           double xu = 0.0, xd = 0.0, xx = 0.0;
-#pragma unroll
-          for (int jj = 0; jj < JW; ++jj) {
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
             const int mm = lane + 64 * jj;
             if (mm < L) {
               xu += 1.0 - dgu[jj];
               xd += 1.0 - dgd[jj];
               xx += (1.0 - dgu[jj]) * (1.0 - dgd[jj]);
             }
-          }
+          });
           nacc_u += wave_sum(xu) / (double)L;
           nacc_d += wave_sum(xd) / (double)L;
           dacc += wave_sum(xx) / (double)L;
           measure_green(gacc);
-          const bool last = (m + 1 == nm) || (((m + 1) * nb) / nm != b) || (w + 1 == d->sweep_end);
+          const bool last = (m + 1 == nm) || (((m + 1) * nb) / nm != b) || (w + 1 == d.sweep_end);
           if (last) {
             double* bp = bins + (size_t)b * NV;
-            if (tid < L) {
-              bp[tid] += gacc[0];
-              bp[L + 1 + tid] += gacc[1];
-            }
+            if (tid < 2 * L) bp[tid + (tid >= L)] += gacc;
             if (tid == 0) {
               bp[L] += nacc_u;
               bp[2 * L + 1] += nacc_d;
@@ -473,42 +501,37 @@ struct Engine {
               bp[2 * L + 3] += nacc_d;
               bp[2 * L + 4] += dacc;
             }
-            gacc[0] = gacc[1] = 0.0;
+            gacc = 0.0;
             nacc_u = nacc_d = dacc = 0.0;
           }
         }
       }
-    } else if (d->op == OP_FORCE) {
-      const int32_t* slices = reinterpret_cast<const int32_t*>(ws + d->off_force);
-      double* ratios = reinterpret_cast<double*>(ws + d->off_force + 4 * ((d->n_force + 1) & ~1));
-      for (int k = 0; k < d->n_force; ++k) {
+    } else if (d.op == OP_FORCE) {
+      const int32_t* slices = reinterpret_cast<const int32_t*>(ws + d.off_force);
+      double* ratios = reinterpret_cast<double*>(ws + d.off_force + 4 * ((d.n_force + 1) & ~1));
+      for (int k = 0; k < d.n_force; ++k) {
         const int l = slices[k];
         const int jj = l >> 6, ln = l & 63;
         const int s = readlane_i(pick<JW>(sv, jj), ln);
-        const double du = s > 0 ? d->dflip_p : d->dflip_m;
-        const double dd = s > 0 ? d->dflip_m : d->dflip_p;
+        const double du = s > 0 ? d.dflip_p : d.dflip_m;
+        const double dd = s > 0 ? d.dflip_m : d.dflip_p;
         const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
         const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
         if (tid == 0) ratios[k] = Ru * Rd;
         rank1(l, du / Ru, dd / Rd);
-        if (lane == ln) {
-#pragma unroll
-          for (int kk = 0; kk < JW; ++kk)
-            if (kk == jj) sv[kk] = -sv[kk];
-        }
+        flip_field(l);
       }
-    } else if (d->op == OP_RECOMPUTE) {
+    } else if (d.op == OP_RECOMPUTE) {
       max_drift = recompute(ws, true);
     }
 
     if (flags & F_SAVE) {
       save_tiles(ws);
       if (wave == 0) {
-#pragma unroll
-        for (int jj = 0; jj < JW; ++jj) {
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) {
           const int m = lane + 64 * jj;
           if (m < L) fields[m] = (int8_t)sv[jj];
-        }
+        });
       }
     }
     if (tid == 0) {
