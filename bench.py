@@ -31,6 +31,19 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 flop/clk/CU
 RECOMPUTE_EVERY = 50
 
+# HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
+# FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
+# valid only for the kernel source with this sha256 prefix.
+PROFILED_KERNEL_SHA = "6dd0dda3d748858e"
+PROFILED_TRAFFIC_BYTES = 1.654e9
+
+
+def kernel_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1006_2716_amd", "csrc", "hfqmc_sweep.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return PROFILED_TRAFFIC_BYTES if sha == PROFILED_KERNEL_SHA else None
+
 
 def algorithmic_flops(L: int, p_acc: float, n_rec: int = RECOMPUTE_EVERY, kbar: float = 0.0) -> float:
     """Flops per proposal, both spins, FMA = 2 flops: rank-one (or flush)
@@ -130,7 +143,7 @@ def main():
     kavg = float(np.mean(kern_ms))
     achieved = flops_launch / (kavg * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=None,
+                    frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=kernel_traffic(),
                     kernel="hfqmc::sweep_kernel<Cfg<64,2>>", kernel_avg_ms=round(kavg, 4),
                     flops_per_launch=flops_launch)
 

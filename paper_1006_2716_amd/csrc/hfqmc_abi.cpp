@@ -61,7 +61,7 @@ int padded_L(int L) { return (L + 15) / 16 * 16; }
 int choose_rt(int LT) {
   const char* e = getenv("HFQMC_RT");
   if (e) {
-    int rt = atoi(e);
+    int rt = strcmp(e, "max") == 0 ? LT / 16 : atoi(e);
     if (find_kernel(LT, rt)) return rt;
   }
   return LT == 64 ? 2 : 1;

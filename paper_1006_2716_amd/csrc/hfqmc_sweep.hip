@@ -120,6 +120,15 @@ struct Cfg {
   static_assert(NTH >= 2 * LT, "measurement needs one thread per (spin, tau_k)");
 };
 
+// Reciprocal to full fp64 precision: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 template <class C>
 struct Stage {
   double col[C::LT];  // column l of G_s
@@ -127,9 +136,16 @@ struct Stage {
 };
 
 template <class C>
+struct StageAll {
+  double col[C::NT][C::LT];    // column (16 tj + l%16) of G_s for every tj
+  double row[C::RT][4][C::LT];  // every row of the owning quad of tile-rows
+};
+
+template <class C>
 struct Smem {
   union {
     Stage<C> stage[2][2];                              // [buffer][spin]
+    StageAll<C> stage_all[2][2];                       // [buffer][spin]
     double dump[(C::DUMP2 ? 2 : 1) * C::LT * C::GS];  // G for the g(tau) estimator
   } u;
   double weiss[2][C::LT];  // Weiss samples, zero padded
@@ -147,7 +163,8 @@ struct Engine {
   // register state
   double g[RT][NT][4];      // this wave's tiles of G_spin
   double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn for slices lane + 64 jj
-  int sv[JW];               // fields for slices lane + 64 jj
+  double fpu[JW], fpd[JW];  // flip factors exp(-2 s lambda s_m) - 1 of those slices
+  int sv[JW];               // fields of those slices
   int buf;                  // staging double-buffer selector (uniform)
   // item constants (uniform), copied out of memory once per item so that
   // barriers (memory clobbers) do not force reloads in the hot loop
@@ -170,76 +187,189 @@ struct Engine {
   // f(rt, tj, r) over this lane's tile elements, all indices compile-time.
   template <class F>
   __device__ __forceinline__ void for_tiles(F&& f) {
-    static_for<RT>([&](auto rt) __attribute__((always_inline)) { static_for<NT>([&](auto tj) __attribute__((always_inline)) { static_for<4>([&](auto r) __attribute__((always_inline)) { f(rt, tj, r); }); }); });
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        static_for<4>([&](auto r) __attribute__((always_inline)) { f(rt, tj, r); });
+      });
+    });
+  }
+  template <class A, class B, class R>
+  __device__ __forceinline__ double gget(A rt, B tj, R r) const {
+    return g[decltype(rt)::value][decltype(tj)::value][decltype(r)::value];
+  }
+  template <class A, class B, class R>
+  __device__ __forceinline__ void gset(A rt, B tj, R r, double x) {
+    g[decltype(rt)::value][decltype(tj)::value][decltype(r)::value] = x;
   }
 
-  // Rank-one update of both spins for slice l with factors fu = d_up/R_up,
-  // fd = d_dn/R_dn:  G_s += f_s (G_s[:,l] - e_l) G_s[l,:].
+  __device__ __forceinline__ void set_field(int jj, int s) {
+    sv[jj] = s;
+    fpu[jj] = s > 0 ? d.dflip_p : d.dflip_m;  // up:   exp(-2 lambda s) - 1
+    fpd[jj] = s > 0 ? d.dflip_m : d.dflip_p;  // down: exp(+2 lambda s) - 1
+  }
+
+  __device__ __forceinline__ void flip_field(int l) {
+    const int jj = l >> 6, ln = l & 63;
+    if (lane == ln)
+      static_for<JW>([&](auto k) __attribute__((always_inline)) {
+        if (k == jj) set_field(k, -sv[k]);
+      });
+  }
+
+  // Owners write column l and row l of their spin's G to the staging buffer.
   // Column l lives in tile-column l/16 of the lanes with c == l%16; row l in
-  // register l%4 of tile-row l/16 of the lanes with q == (l%16)/4.  Uniform
-  // branches over compile-time indices pick the values to stage, so only the
-  // needed values travel through LDS and no register is indexed at run time.
-  __device__ __forceinline__ void rank1(int l, double fu, double fd) {
+  // register l%4 of tile-row l/16 of the lanes with q == (l%16)/4.
+#ifndef HFQMC_STAGE_ALL
+  // Uniform branches over compile-time indices pick the values to stage: the
+  // lanes with c == l%16 publish column l at this wave's rows, the lanes with
+  // q == (l%16)/4 of the wave owning tile-row l/16 publish row l.
+  __device__ __forceinline__ void stage(int l) {
     const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2, rl = l & 3;
-    const int rtl = tl % RT;
     Stage<C>& mine = sm.u.stage[buf][spin];
     if (c == cl) {
       static_for<NT>([&](auto tj) __attribute__((always_inline)) {
-        if (tj == tl) static_for<RT>([&](auto rt) __attribute__((always_inline)) { static_for<4>([&](auto r) __attribute__((always_inline)) { mine.col[row_of(rt, r)] = g[rt][tj][r]; }); });
-      });
-    }
-    if (q == ql && tl / RT == wr) {
-      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
-        if (rt == rtl)
-          static_for<4>([&](auto r) __attribute__((always_inline)) {
-            if (r == rl) static_for<NT>([&](auto tj) __attribute__((always_inline)) { mine.row[tj * 16 + c] = g[rt][tj][r]; });
+        if (tj == tl)
+          static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+            static_for<4>([&](auto r) __attribute__((always_inline)) { mine.col[row_of(rt, r)] = gget(rt, tj, r); });
           });
       });
     }
-    __syncthreads();
+    if (q == ql && tl / RT == wr) {
+      const int rtl = tl % RT;
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        if (rt == rtl)
+          static_for<4>([&](auto r) __attribute__((always_inline)) {
+            if (r == rl)
+              static_for<NT>([&](auto tj) __attribute__((always_inline)) { mine.row[tj * 16 + c] = gget(rt, tj, r); });
+          });
+      });
+    }
+  }
+#else
+  // Owners write every candidate (all tile-columns / all quad rows); readers
+  // select by address.  No register is selected at run time.
+  __device__ __forceinline__ void stage(int l) {
+    const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2;
+    StageAll<C>& mine = sm.u.stage_all[buf][spin];
+    if (c == cl)
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+        mine.col[tj][row_of(rt, r)] = gget(rt, tj, r);
+      });
+    if (q == ql && tl / RT == wr)
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+        mine.row[rt][r][tj * 16 + c] = gget(rt, tj, r);
+      });
+  }
+#endif
+#ifndef HFQMC_STAGE_ALL
+  __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.stage[buf][s].col; }
+  __device__ __forceinline__ const double* rowp(int s, int l) const { return sm.u.stage[buf][s].row; }
+#else
+  __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.stage_all[buf][s].col[l >> 4]; }
+  __device__ __forceinline__ const double* rowp(int s, int l) const {
+    return sm.u.stage_all[buf][s].row[(l >> 4) % RT][l & 3];
+  }
+#endif
+
+  // After the barrier: read this lane's a = f (G[:,l] - e_l) and b = G[l,:]
+  // values and advance both diagonal copies by the same rank-one term.
+  __device__ __forceinline__ void fetch(int l, double fu, double fd, double (&a)[RT][4], double (&b)[NT]) {
+    const double* row = rowp(spin, l);
     const double f = spin == 0 ? fu : fd;
-    double a[RT][4], b[NT];
+    const double* col = colp(spin, l);
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<4>([&](auto r) __attribute__((always_inline)) { a[rt][r] = col[row_of(rt, r)]; });
+    });
     static_for<RT>([&](auto rt) __attribute__((always_inline)) {
       static_for<4>([&](auto r) __attribute__((always_inline)) {
         const int i = row_of(rt, r);
-        double x = mine.col[i];
+        double x = a[rt][r];
         if (i == l) x -= 1.0;
         a[rt][r] = f * x;
       });
     });
-    static_for<NT>([&](auto tj) __attribute__((always_inline)) { b[tj] = mine.row[tj * 16 + c]; });
-    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = __builtin_fma(a[rt][r], b[tj], g[rt][tj][r]); });
-    // the same update applied to this wave's copies of both diagonals
-    const Stage<C>& su = sm.u.stage[buf][0];
-    const Stage<C>& sd = sm.u.stage[buf][1];
+    static_for<NT>([&](auto tj) __attribute__((always_inline)) { b[tj] = row[tj * 16 + c]; });
+    const double *cu = colp(0, l), *cd = colp(1, l), *ru = rowp(0, l), *rd = rowp(1, l);
     static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
       if (m < LT) {
-        double xu = su.col[m], xd = sd.col[m];
+        double xu = cu[m], xd = cd[m];
         if (m == l) {
           xu -= 1.0;
           xd -= 1.0;
         }
-        dgu[jj] = __builtin_fma(fu * xu, su.row[m], dgu[jj]);
-        dgd[jj] = __builtin_fma(fd * xd, sd.row[m], dgd[jj]);
+        dgu[jj] = __builtin_fma(fu * xu, ru[m], dgu[jj]);
+        dgd[jj] = __builtin_fma(fd * xd, rd[m], dgd[jj]);
       }
     });
     buf ^= 1;
   }
 
+  __device__ __forceinline__ void apply(const double (&a)[RT][4], const double (&b)[NT]) {
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      gset(rt, tj, r, __builtin_fma(a[rt][r], b[tj], gget(rt, tj, r)));
+    });
+  }
+
+  // G_s += f_s (G_s[:,l] - e_l) G_s[l,:] for both spins (one barrier).
+  __device__ __forceinline__ void rank1(int l, double fu, double fd) {
+    double a[RT][4], b[NT];
+    stage(l);
+    __syncthreads();
+    fetch(l, fu, fd, a, b);
+    apply(a, b);
+  }
+
+  // Vectorised Metropolis scan over slices [l0, L): rejections leave G
+  // unchanged, so every remaining slice is tested against the current
+  // diagonals at once (lane m tests slice m with exactly the arithmetic of a
+  // sequential scan) and the first accepted slice is found by a wave ballot.
+  // Returns that slice (L if none) and its factors f_s = d_s / R_s.
+  __device__ __forceinline__ int scan(int l0, const double (&uv)[JW], double& fu, double& fd, int64_t& nonpos,
+                                      int64_t& err) {
+    uint64_t acc_mask[JW], bad_mask[JW];
+    double Ru[JW], Rd[JW];
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      const int m = lane + 64 * jj;
+      const bool live = m >= l0 && m < L;
+      Ru[jj] = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
+      Rd[jj] = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
+      const double R = Ru[jj] * Rd[jj];
+      acc_mask[jj] = __ballot(live && uv[jj] < R);
+      bad_mask[jj] = __ballot(live && !(R > 0.0));
+    });
+    int l = L;
+    static_for<JW>([&](auto k) __attribute__((always_inline)) {
+      constexpr int jj = JW - 1 - decltype(k)::value;  // highest word first, lowest wins
+      if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
+    });
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      const int hi = l - 64 * jj;  // slices below l were rejected
+      const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
+      const uint64_t bad = bad_mask[jj] & below;
+      nonpos += __builtin_popcountll(bad);
+      if (bad) err = 1;  // R <= 0 or NaN: impossible in exact arithmetic
+    });
+    const int ls = l < L ? l : 0, jj = ls >> 6, ln = ls & 63;
+    const double ru = readlane_d(pick<JW>(Ru, jj), ln), rd = readlane_d(pick<JW>(Rd, jj), ln);
+    fu = readlane_d(pick<JW>(fpu, jj), ln) * recip(ru);
+    fd = readlane_d(pick<JW>(fpd, jj), ln) * recip(rd);
+    return l;
+  }
+
   // Rebuild the diagonal copies from the tiles (after loading saved state).
   __device__ __forceinline__ void diag_from_tiles() {
     __syncthreads();
-    double* dst = sm.u.stage[0][spin].col;
+    double* dst = sm.u.dump + spin * LT;
     for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
       const int i = row_of(rt, r), j = tj * 16 + c;
-      if (i == j) dst[i] = g[rt][tj][r];
+      if (i == j) dst[i] = gget(rt, tj, r);
     });
     __syncthreads();
     static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
-      dgu[jj] = m < LT ? sm.u.stage[0][0].col[m] : 0.0;
-      dgd[jj] = m < LT ? sm.u.stage[0][1].col[m] : 0.0;
+      dgu[jj] = m < LT ? sm.u.dump[m] : 0.0;
+      dgd[jj] = m < LT ? sm.u.dump[LT + m] : 0.0;
     });
     __syncthreads();
   }
@@ -252,12 +382,16 @@ struct Engine {
 
   __device__ __forceinline__ void save_tiles(uint8_t* ws) {
     double* p = state_ptr(ws);
-    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { p[(rt * NT + tj) * 4 + r] = g[rt][tj][r]; });
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      p[(rt * NT + tj) * 4 + r] = gget(rt, tj, r);
+    });
   }
 
   __device__ __forceinline__ void load_tiles(uint8_t* ws) {
     const double* p = state_ptr(ws);
-    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = p[(rt * NT + tj) * 4 + r]; });
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      gset(rt, tj, r, p[(rt * NT + tj) * 4 + r]);
+    });
   }
 
   // Dyson equation from scratch: G = G0, then switch every slice's potential
@@ -278,7 +412,9 @@ struct Engine {
       __syncthreads();
       if (spin == s) {
         const double* src = sm.u.dump + row_of(0, 0) * GS + c;
-        for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { g[rt][tj][r] = src[(rt * 16 + r) * GS + tj * 16]; });
+        for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+          gset(rt, tj, r, src[(rt * 16 + r) * GS + tj * 16]);
+        });
       }
     });
     __syncthreads();
@@ -297,12 +433,14 @@ struct Engine {
       const double dd = s > 0 ? d.dset_m : d.dset_p;  // down: V_l = -lambda s_l
       const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
       const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
-      rank1(l, du / Ru, dd / Rd);
+      rank1(l, du * recip(Ru), dd * recip(Rd));
     }
     double dr = 0.0;
     if (drift) {
       const double* p = state_ptr(ws);
-      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - g[rt][tj][r])); });
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+        dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - gget(rt, tj, r)));
+      });
       dr = wave_max(dr);
       if (lane == 0) sm.red[wave] = dr;
       __syncthreads();
@@ -342,7 +480,9 @@ struct Engine {
 
   __device__ __forceinline__ void dump_tiles(double* m) {
     double* dst = m + row_of(0, 0) * GS + c;
-    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) { dst[(rt * 16 + r) * GS + tj * 16] = g[rt][tj][r]; });
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      dst[(rt * 16 + r) * GS + tj * 16] = gget(rt, tj, r);
+    });
   }
 
   __device__ __forceinline__ void measure_green(double& gacc) {
@@ -363,14 +503,6 @@ struct Engine {
       });
     }
     __syncthreads();  // the next staging write reuses the dump area
-  }
-
-  __device__ __forceinline__ void flip_field(int l) {
-    const int jj = l >> 6, ln = l & 63;
-    if (lane == ln)
-      static_for<JW>([&](auto k) __attribute__((always_inline)) {
-        if (k == jj) sv[k] = -sv[k];
-      });
   }
 
   __device__ __forceinline__ void run(const ImpDesc* desc, uint8_t* ws) {
@@ -398,11 +530,11 @@ struct Engine {
     if (flags & (F_FIELDS_GIVEN | F_RESUME)) {
       static_for<JW>([&](auto jj) __attribute__((always_inline)) {
         const int m = lane + 64 * jj;
-        sv[jj] = m < L ? (fields[m] < 0 ? -1 : 1) : 1;
+        set_field(jj, m < L ? (fields[m] < 0 ? -1 : 1) : 1);
       });
     } else {
       const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d.seed, d.site);
-      static_for<JW>([&](auto jj) __attribute__((always_inline)) { sv[jj] = (x.v[jj] >> 63) ? -1 : 1; });
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) { set_field(jj, (x.v[jj] >> 63) ? -1 : 1); });
     }
     __syncthreads();
     if (flags & F_RESUME) {
@@ -420,6 +552,7 @@ struct Engine {
       double gacc = 0.0;  // thread t < 2L: running bin sum of g_s(tau_k), s = t / L, k = t % L
       double nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
       const int64_t nm = d.n_measure, nb = d.n_bins;
+      int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
         double uv[JW];
         {
@@ -427,54 +560,31 @@ struct Engine {
                                         d.site);
           static_for<JW>([&](auto jj) __attribute__((always_inline)) { uv[jj] = u01(x.v[jj]); });
         }
-        // Rejections leave G unchanged, so the decisions of all remaining
-        // slices can be taken at once against the current diagonals: lane m
-        // tests slice m (u_m < R_m, the same arithmetic as a sequential scan)
-        // and the first accepted slice is found with a wave ballot.  Only
-        // accepted flips pay for an update.
+        double fu, fd;
+        int l = scan(0, uv, fu, fd, nonpos, err);
         int l0 = 0;
-        for (;;) {
-          uint64_t acc_mask[JW], bad_mask[JW];
-          double fu_v[JW], fd_v[JW];
-          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-            const int m = lane + 64 * jj;
-            const bool live = m >= l0 && m < L;
-            const double du = sv[jj] > 0 ? d.dflip_p : d.dflip_m;
-            const double dd = sv[jj] > 0 ? d.dflip_m : d.dflip_p;
-            const double Ru = __builtin_fma(1.0 - dgu[jj], du, 1.0), Rd = __builtin_fma(1.0 - dgd[jj], dd, 1.0);
-            const double R = Ru * Rd;
-            acc_mask[jj] = __ballot(live && uv[jj] < R);
-            bad_mask[jj] = __ballot(live && !(R > 0.0));
-            if (__ballot(live && !(R == R))) err = 1;  // non-finite ratio
-            fu_v[jj] = du / Ru;
-            fd_v[jj] = dd / Rd;
-          });
-          int l = L;
-          static_for<JW>([&](auto k) __attribute__((always_inline)) {
-            constexpr int jj = JW - 1 - decltype(k)::value;  // highest word first, lowest wins
-            if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
-          });
-          // slices [l0, l] were proposed; those with R <= 0 were rejected
-          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-            const int hi = l - 64 * jj;
-            const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
-            nonpos += __builtin_popcountll(bad_mask[jj] & below);
-          });
-          if (l >= L) {
-            proposals += L - l0;
-            break;
-          }
-          proposals += l - l0 + 1;
-          const int jj = l >> 6, ln = l & 63;
-          rank1(l, readlane_d(pick<JW>(fu_v, jj), ln), readlane_d(pick<JW>(fd_v, jj), ln));
+        while (l < L) {
+          // accepted flip of slice l: stage, then the rank-one update; the
+          // scan for the next accepted slice only needs the new diagonals,
+          // so it is issued before the tile FMAs to overlap their latency
+          double a[RT][4], b[NT];
+          stage(l);
+          __syncthreads();
+          fetch(l, fu, fd, a, b);
           flip_field(l);
+          proposals += l - l0 + 1;
           ++accepts;
           l0 = l + 1;
+          l = scan(l0, uv, fu, fd, nonpos, err);
+          apply(a, b);
         }
-        const int64_t wl = w;  // request-local sweep index
-        if ((wl + 1) % d.recompute_every == 0) max_drift = fmax(max_drift, recompute(ws, true));
-        if (wl >= d.n_warmup) {
-          const int64_t m = wl - d.n_warmup;
+        proposals += L - l0;
+        if (w == next_rec) {
+          max_drift = fmax(max_drift, recompute(ws, true));
+          next_rec += d.recompute_every;
+        }
+        if (w >= d.n_warmup) {
+          const int64_t m = w - d.n_warmup;
           const int64_t b = (m * nb) / nm;
           // density and double occupancy from the diagonals
           double xu = 0.0, xd = 0.0, xx = 0.0;
@@ -512,13 +622,11 @@ struct Engine {
       for (int k = 0; k < d.n_force; ++k) {
         const int l = slices[k];
         const int jj = l >> 6, ln = l & 63;
-        const int s = readlane_i(pick<JW>(sv, jj), ln);
-        const double du = s > 0 ? d.dflip_p : d.dflip_m;
-        const double dd = s > 0 ? d.dflip_m : d.dflip_p;
         const double Gu = readlane_d(pick<JW>(dgu, jj), ln), Gd = readlane_d(pick<JW>(dgd, jj), ln);
+        const double du = readlane_d(pick<JW>(fpu, jj), ln), dd = readlane_d(pick<JW>(fpd, jj), ln);
         const double Ru = __builtin_fma(1.0 - Gu, du, 1.0), Rd = __builtin_fma(1.0 - Gd, dd, 1.0);
         if (tid == 0) ratios[k] = Ru * Rd;
-        rank1(l, du / Ru, dd / Rd);
+        rank1(l, du * recip(Ru), dd * recip(Rd));
         flip_field(l);
       }
     } else if (d.op == OP_RECOMPUTE) {
@@ -578,8 +686,8 @@ static KernelInfo info() {
 }
 
 static const KernelInfo kKernels[] = {
-    info<16, 1>(), info<32, 1>(), info<48, 1>(), info<64, 1>(), info<64, 2>(), info<80, 1>(),
-    info<96, 1>(), info<96, 2>(), info<112, 1>(), info<128, 1>(), info<128, 2>(),
+    info<16, 1>(), info<32, 1>(), info<32, 2>(), info<48, 1>(), info<48, 3>(), info<64, 1>(), info<64, 2>(),
+    info<64, 4>(), info<80, 1>(), info<96, 1>(), info<96, 2>(), info<112, 1>(), info<128, 1>(), info<128, 2>(),
 };
 
 const KernelInfo* find_kernel(int LT, int RT) {
