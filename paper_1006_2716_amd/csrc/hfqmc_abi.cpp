@@ -21,7 +21,7 @@
 
 namespace hfqmc {
 struct KernelInfo;
-const KernelInfo* find_kernel(int LT, int RT);
+const KernelInfo* find_kernel(int LT, int RT, int DK);
 int kernel_threads(const KernelInfo* k);
 size_t kernel_lds(const KernelInfo* k);
 hipError_t kernel_occupancy(const KernelInfo* k, int* blocks_per_cu);
@@ -57,14 +57,22 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
-// Tile-rows per wave for a padded slice count (environment override for tuning).
-int choose_rt(int LT) {
+// Tile-rows per wave for a padded slice count and update kind (environment
+// override for tuning experiments).
+int choose_rt(int LT, int DK = 0) {
   const char* e = getenv("HFQMC_RT");
-  if (e) {
+  if (e && DK == 0) {
     int rt = strcmp(e, "max") == 0 ? LT / 16 : atoi(e);
-    if (find_kernel(LT, rt)) return rt;
+    if (find_kernel(LT, rt, 0)) return rt;
   }
   return LT == 64 ? 2 : 1;
+}
+
+// Update kind of a problem: 0 plain rank-one, 1 delayed fp64, 2 delayed mixed.
+int update_kind(const hfqmc_problem& p, hfqmc_precision prec) {
+  const int k = p.delay == 0 ? 1 : p.delay;
+  if (k <= 1) return 0;
+  return prec == HFQMC_MIXED ? 2 : 1;
 }
 
 // HS coupling from cosh(lambda) = exp(dtau U / 2), written as
@@ -349,7 +357,7 @@ hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d) {
   d.off_state = (int64_t)s->o_state;
   d.off_force = (int64_t)s->o_force;
   d.LT = s->LT;
-  const KernelInfo* k = find_kernel(s->LT, s->RT);
+  const KernelInfo* k = find_kernel(s->LT, s->RT, 0);
   if (!k) return fail(HFQMC_EINVAL, "no kernel for LT=%d RT=%d", s->LT, s->RT);
   const size_t qoff = s->o_force + align_up(1024 * (sizeof(int32_t) + sizeof(double)), 256);
   struct {
@@ -435,21 +443,29 @@ hfqmc_status hfqmc_stage(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* 
   if (ws_bytes < lo.total) return fail(HFQMC_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, lo.total);
   if (hfqmc_status s = set_device(c)) return s;
 
-  // group items by kernel class; order items inside a class by descending work
-  std::vector<int> idx(n);
-  for (int i = 0; i < n; ++i) idx[i] = i;
+  // group items by kernel class (padded L, update kind); inside a class order
+  // items by descending work
+  std::vector<int> idx(n), kind(n);
+  for (int i = 0; i < n; ++i) {
+    idx[i] = i;
+    kind[i] = update_kind(p[i], c->prec);
+    if (kind[i] && !find_kernel(padded_L(p[i].L), choose_rt(padded_L(p[i].L), kind[i]), kind[i]))
+      return fail(HFQMC_EINVAL, "problem %d: no delayed-update kernel for L=%d", i, p[i].L);
+    if (p[i].delay > 32) return fail(HFQMC_EINVAL, "problem %d: delay %d > 32", i, p[i].delay);
+  }
   auto cost = [&](int i) { return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * p[i].L; };
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
     const int la = padded_L(p[a].L), lb = padded_L(p[b].L);
     if (la != lb) return la > lb;
+    if (kind[a] != kind[b]) return kind[a] < kind[b];
     return cost(a) > cost(b);
   });
   std::vector<Group> groups;
   for (int k = 0; k < n;) {
-    const int LT = padded_L(p[idx[k]].L);
+    const int LT = padded_L(p[idx[k]].L), DK = kind[idx[k]];
     int e = k;
-    while (e < n && padded_L(p[idx[e]].L) == LT) ++e;
-    const KernelInfo* ki = find_kernel(LT, choose_rt(LT));
+    while (e < n && padded_L(p[idx[e]].L) == LT && kind[idx[e]] == DK) ++e;
+    const KernelInfo* ki = find_kernel(LT, choose_rt(LT, DK), DK);
     if (!ki) return fail(HFQMC_EINVAL, "no kernel for padded L=%d", LT);
     int bpc = 0;
     HIP_TRY(kernel_occupancy(ki, &bpc));

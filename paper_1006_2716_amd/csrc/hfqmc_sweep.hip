@@ -104,10 +104,16 @@ __device__ __forceinline__ T pick(const T (&a)[JW], int jj) {
 }
 
 // ------------------------------------------------------------- configuration
-template <int LT_, int RT_>
+// DK_: 0 = Sherman-Morrison rank-one updates applied to the tiles at once;
+// 1 = delayed rank-k updates flushed by v_mfma_f64_16x16x4f64; 2 = delayed
+// updates whose product is formed by v_mfma_f32_16x16x4f32 (fp32 operands,
+// fp32 product) and added into the fp64 tiles.
+template <int LT_, int RT_, int DK_ = 0>
 struct Cfg {
   static constexpr int LT = LT_;          // padded slice count (multiple of 16)
   static constexpr int RT = RT_;          // tile-rows per wave
+  static constexpr int DK = DK_;
+  static constexpr int KP = DK ? 32 : 1;  // panel capacity (largest delay depth)
   static constexpr int NT = LT / 16;      // tiles per matrix dimension
   static constexpr int WPS = NT / RT;     // waves per spin
   static constexpr int NW = 2 * WPS;      // waves per workgroup
@@ -136,16 +142,14 @@ struct Stage {
 };
 
 template <class C>
-struct StageAll {
-  double col[C::NT][C::LT];    // column (16 tj + l%16) of G_s for every tj
-  double row[C::RT][4][C::LT];  // every row of the owning quad of tile-rows
-};
-
-template <class C>
 struct Smem {
+  struct Work {
+    Stage<C> stage[2][2];            // [buffer][spin]
+    double pa[2][C::KP][C::LT];      // delayed updates: scaled columns a_j of each spin
+    double pb[2][C::KP][C::LT];      // delayed updates: rows b_j of each spin
+  };
   union {
-    Stage<C> stage[2][2];                              // [buffer][spin]
-    StageAll<C> stage_all[2][2];                       // [buffer][spin]
+    Work w;
     double dump[(C::DUMP2 ? 2 : 1) * C::LT * C::GS];  // G for the g(tau) estimator
   } u;
   double weiss[2][C::LT];  // Weiss samples, zero padded
@@ -166,6 +170,8 @@ struct Engine {
   double fpu[JW], fpd[JW];  // flip factors exp(-2 s lambda s_m) - 1 of those slices
   int sv[JW];               // fields of those slices
   int buf;                  // staging double-buffer selector (uniform)
+  int kb = 0;               // delayed updates pending in the panels (uniform)
+  int kdepth = 1;           // flush when kb reaches this depth
   // item constants (uniform), copied out of memory once per item so that
   // barriers (memory clobbers) do not force reloads in the hot loop
   int L;
@@ -219,13 +225,12 @@ struct Engine {
   // Owners write column l and row l of their spin's G to the staging buffer.
   // Column l lives in tile-column l/16 of the lanes with c == l%16; row l in
   // register l%4 of tile-row l/16 of the lanes with q == (l%16)/4.
-#ifndef HFQMC_STAGE_ALL
   // Uniform branches over compile-time indices pick the values to stage: the
   // lanes with c == l%16 publish column l at this wave's rows, the lanes with
   // q == (l%16)/4 of the wave owning tile-row l/16 publish row l.
   __device__ __forceinline__ void stage(int l) {
     const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2, rl = l & 3;
-    Stage<C>& mine = sm.u.stage[buf][spin];
+    Stage<C>& mine = sm.u.w.stage[buf][spin];
     if (c == cl) {
       static_for<NT>([&](auto tj) __attribute__((always_inline)) {
         if (tj == tl)
@@ -245,31 +250,8 @@ struct Engine {
       });
     }
   }
-#else
-  // Owners write every candidate (all tile-columns / all quad rows); readers
-  // select by address.  No register is selected at run time.
-  __device__ __forceinline__ void stage(int l) {
-    const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2;
-    StageAll<C>& mine = sm.u.stage_all[buf][spin];
-    if (c == cl)
-      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
-        mine.col[tj][row_of(rt, r)] = gget(rt, tj, r);
-      });
-    if (q == ql && tl / RT == wr)
-      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
-        mine.row[rt][r][tj * 16 + c] = gget(rt, tj, r);
-      });
-  }
-#endif
-#ifndef HFQMC_STAGE_ALL
-  __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.stage[buf][s].col; }
-  __device__ __forceinline__ const double* rowp(int s, int l) const { return sm.u.stage[buf][s].row; }
-#else
-  __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.stage_all[buf][s].col[l >> 4]; }
-  __device__ __forceinline__ const double* rowp(int s, int l) const {
-    return sm.u.stage_all[buf][s].row[(l >> 4) % RT][l & 3];
-  }
-#endif
+  __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.w.stage[buf][s].col; }
+  __device__ __forceinline__ const double* rowp(int s, int l) const { return sm.u.w.stage[buf][s].row; }
 
   // After the barrier: read this lane's a = f (G[:,l] - e_l) and b = G[l,:]
   // values and advance both diagonal copies by the same rank-one term.
@@ -318,6 +300,86 @@ struct Engine {
     __syncthreads();
     fetch(l, fu, fd, a, b);
     apply(a, b);
+  }
+
+  // ---- delayed rank-k updates: G = G0 + A B^T with G0 in the tiles ----
+  // Column l and row l of the current G are the staged G0 column/row plus the
+  // pending terms; the new scaled column a = f (G[:,l] - e_l) and row b =
+  // G[l,:] are appended as panel columns, and the diagonal copies advance by
+  // a_m b_m.  Work items (spin, column|row, index) are spread over the
+  // workgroup.
+  __device__ __forceinline__ void delayed_append(int l, double fu, double fd) {
+    auto& W = sm.u.w;
+    for (int it = tid; it < 4 * LT; it += C::NTH) {
+      const int s = it / (2 * LT), v = (it / LT) & 1, i = it % LT;
+      if (i >= L) {  // padding rows/columns stay exactly zero
+        (v == 0 ? W.pa : W.pb)[s][kb][i] = 0.0;
+      } else if (v == 0) {
+        double x = W.stage[buf][s].col[i];
+        for (int j = 0; j < kb; ++j) x = __builtin_fma(W.pa[s][j][i], W.pb[s][j][l], x);
+        if (i == l) x -= 1.0;
+        W.pa[s][kb][i] = (s ? fd : fu) * x;
+      } else {
+        double x = W.stage[buf][s].row[i];
+        for (int j = 0; j < kb; ++j) x = __builtin_fma(W.pa[s][j][l], W.pb[s][j][i], x);
+        W.pb[s][kb][i] = x;
+      }
+    }
+    __syncthreads();
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      const int m = lane + 64 * jj;
+      if (m < L) {
+        dgu[jj] = __builtin_fma(W.pa[0][kb][m], W.pb[0][kb][m], dgu[jj]);
+        dgd[jj] = __builtin_fma(W.pa[1][kb][m], W.pb[1][kb][m], dgd[jj]);
+      }
+    });
+    ++kb;
+    buf ^= 1;
+  }
+
+  // G0 += A B^T over the kb pending updates, four at a time on the matrix
+  // cores.  Lane (i, kk) = (lane % 16, lane / 16) feeds A[row i][kk] and
+  // B^T[kk][col i].  The fp64 instruction keeps tile row 4*r + q in lane
+  // (q, c) register r, the fp32 one row 4*q + r (the tile layout), so for
+  // fp64 the A rows are fed transposed within each 4 x 4 block.
+  __device__ __forceinline__ void flush() {
+    if constexpr (C::DK != 0) {
+      if (kb == 0) return;
+      const auto& W = sm.u.w;
+      const int ii = lane & 15, kk = lane >> 4;
+      const int arow = C::DK == 1 ? 4 * (ii & 3) + (ii >> 2) : ii;
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        const int ti = wr * RT + rt;
+        static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+          if constexpr (C::DK == 1) {
+            typedef double d4 __attribute__((ext_vector_type(4)));
+            d4 acc = {gget(rt, tj, std::integral_constant<int, 0>{}), gget(rt, tj, std::integral_constant<int, 1>{}),
+                      gget(rt, tj, std::integral_constant<int, 2>{}), gget(rt, tj, std::integral_constant<int, 3>{})};
+            for (int k0 = 0; k0 < kb; k0 += 4) {
+              const int k = k0 + kk;
+              const double av = k < kb ? W.pa[spin][k][ti * 16 + arow] : 0.0;
+              const double bv = k < kb ? W.pb[spin][k][tj * 16 + ii] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+            static_for<4>([&](auto r) __attribute__((always_inline)) { gset(rt, tj, r, acc[decltype(r)::value]); });
+          } else {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int k0 = 0; k0 < kb; k0 += 4) {
+              const int k = k0 + kk;
+              const float av = k < kb ? (float)W.pa[spin][k][ti * 16 + arow] : 0.f;
+              const float bv = k < kb ? (float)W.pb[spin][k][tj * 16 + ii] : 0.f;
+              acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            }
+            static_for<4>([&](auto r) __attribute__((always_inline)) {
+              gset(rt, tj, r, gget(rt, tj, r) + (double)acc[decltype(r)::value]);
+            });
+          }
+        });
+      });
+      __syncthreads();  // the panels are reused after this
+      kb = 0;
+    }
   }
 
   // Vectorised Metropolis scan over slices [l0, L): rejections leave G
@@ -508,6 +570,8 @@ struct Engine {
   __device__ __forceinline__ void run(const ImpDesc* desc, uint8_t* ws) {
     d = *desc;
     L = d.L;
+    kdepth = d.delay < 1 ? 1 : (d.delay > C::KP ? C::KP : d.delay);
+    kb = 0;
     const int flags = d.flags;
     const int NV = n_values(L);
     double* bins = reinterpret_cast<double*>(ws + d.off_bins);
@@ -564,20 +628,33 @@ struct Engine {
         int l = scan(0, uv, fu, fd, nonpos, err);
         int l0 = 0;
         while (l < L) {
-          // accepted flip of slice l: stage, then the rank-one update; the
-          // scan for the next accepted slice only needs the new diagonals,
-          // so it is issued before the tile FMAs to overlap their latency
-          double a[RT][4], b[NT];
-          stage(l);
-          __syncthreads();
-          fetch(l, fu, fd, a, b);
-          flip_field(l);
-          proposals += l - l0 + 1;
-          ++accepts;
-          l0 = l + 1;
-          l = scan(l0, uv, fu, fd, nonpos, err);
-          apply(a, b);
+          if constexpr (C::DK == 0) {
+            // accepted flip of slice l: stage, then the rank-one update; the
+            // scan for the next accepted slice only needs the new diagonals,
+            // so it is issued before the tile FMAs to overlap their latency
+            double a[RT][4], b[NT];
+            stage(l);
+            __syncthreads();
+            fetch(l, fu, fd, a, b);
+            flip_field(l);
+            proposals += l - l0 + 1;
+            ++accepts;
+            l0 = l + 1;
+            l = scan(l0, uv, fu, fd, nonpos, err);
+            apply(a, b);
+          } else {
+            stage(l);
+            __syncthreads();
+            delayed_append(l, fu, fd);
+            if (kb >= kdepth) flush();
+            flip_field(l);
+            proposals += l - l0 + 1;
+            ++accepts;
+            l0 = l + 1;
+            l = scan(l0, uv, fu, fd, nonpos, err);
+          }
         }
+        flush();
         proposals += L - l0;
         if (w == next_rec) {
           max_drift = fmax(max_drift, recompute(ws, true));
@@ -674,25 +751,28 @@ __global__ void zero_kernel(uint64_t* __restrict__ p, size_t n) {
 
 // ------------------------------------------------------------- host dispatch
 struct KernelInfo {
-  int LT, RT, threads;
+  int LT, RT, DK, threads;
   size_t lds;
   const void* fn;
 };
 
-template <int LT, int RT>
+template <int LT, int RT, int DK = 0>
 static KernelInfo info() {
-  using C = Cfg<LT, RT>;
-  return KernelInfo{LT, RT, C::NTH, sizeof(Smem<C>), reinterpret_cast<const void*>(&sweep_kernel<C>)};
+  using C = Cfg<LT, RT, DK>;
+  return KernelInfo{LT, RT, DK, C::NTH, sizeof(Smem<C>), reinterpret_cast<const void*>(&sweep_kernel<C>)};
 }
 
 static const KernelInfo kKernels[] = {
     info<16, 1>(), info<32, 1>(), info<32, 2>(), info<48, 1>(), info<48, 3>(), info<64, 1>(), info<64, 2>(),
     info<64, 4>(), info<80, 1>(), info<96, 1>(), info<96, 2>(), info<112, 1>(), info<128, 1>(), info<128, 2>(),
+    // delayed rank-k updates, fp64 and mixed-precision flushes
+    info<32, 1, 1>(), info<48, 1, 1>(), info<64, 2, 1>(), info<80, 1, 1>(), info<96, 1, 1>(), info<128, 1, 1>(),
+    info<32, 1, 2>(), info<48, 1, 2>(), info<64, 2, 2>(), info<80, 1, 2>(), info<96, 1, 2>(), info<128, 1, 2>(),
 };
 
-const KernelInfo* find_kernel(int LT, int RT) {
+const KernelInfo* find_kernel(int LT, int RT, int DK) {
   for (const auto& k : kKernels)
-    if (k.LT == LT && k.RT == RT) return &k;
+    if (k.LT == LT && k.RT == RT && k.DK == DK) return &k;
   return nullptr;
 }
 
