@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-single", action="store_true", help="skip the single-impurity comparison")
+    ap.add_argument("--delay", type=int, default=1,
+                    help="update depth: 1 rank-one (default, measured fastest), 2..32 delayed rank-k")
+    ap.add_argument("--mixed", action="store_true", help="fp32 delayed-update products (with --delay > 1)")
+    ap.add_argument("--graph", action="store_true", help="replay the pass from a captured hipGraph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -110,24 +114,29 @@ def main():
     from paper_1006_2716_amd import hfqmc, workloads
 
     probs = workloads.chain_batch_L64()
+    for p in probs:
+        p["delay"] = args.delay
     n_imp = len(probs)
     L = probs[0]["L"]
-    ctx = hfqmc.Context(0)
+    ctx = hfqmc.Context(0, precision=hfqmc.MIXED if args.mixed else hfqmc.FP64)
     ws = ctx.alloc_workspace(probs)
     ctx.stage(probs, ws)
+    rt, k, _ = ctx.plan(L, args.delay)
+    run = ctx.run_graph if args.graph else ctx.run
 
     for _ in range(args.warmup):
-        ctx.run()
+        run()
     torch.cuda.synchronize()
 
     step_ms, kern_ms = [], []
     t_start = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        ctx.run()
+        run()
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - t0) * 1e3)
-        kern_ms.append(ctx.last_run_ms()[0])
+        # the sweep kernel's own events (the whole pass when replayed from a graph)
+        kern_ms.append(ctx.last_run_ms()[0] if args.graph else ctx.last_launch_ms(0)[0])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
@@ -139,12 +148,15 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = proposals / (ms_per_step * 1e-3)
 
-    flops_launch = proposals * algorithmic_flops(L, p_acc)
+    kbar = 0.0 if k <= 1 else (k - 1) / 2.0  # mean pending updates while appending
+    flops_launch = proposals * algorithmic_flops(L, p_acc, kbar=kbar)
     kavg = float(np.mean(kern_ms))
     achieved = flops_launch / (kavg * 1e-3) / 1e12
+    dk = 0 if k <= 1 else (2 if args.mixed else 1)
+    traffic = kernel_traffic() if (k <= 1 and not args.graph) else None
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=kernel_traffic(),
-                    kernel="hfqmc::sweep_kernel<Cfg<64,2>>", kernel_avg_ms=round(kavg, 4),
+                    frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=traffic,
+                    kernel=f"hfqmc::sweep_kernel<Cfg<64,{rt},{dk}>>", kernel_avg_ms=round(kavg, 4),
                     flops_per_launch=flops_launch)
 
     out = {
@@ -160,13 +172,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not args.mixed else "f64+f32 (delayed products)",
         "data": "synthetic",
         "config": {"workload": "512 impurities x L=64 (beta=8, dtau=0.125), U~U[4,12], open 64-site chain "
-                               "centre-site Weiss at mu_eff~U[-1,1], 200+2000 sweeps, fp64, plain SM updates",
+                               "centre-site Weiss at mu_eff~U[-1,1], 200+2000 sweeps, "
+                               + ("rank-one SM updates" if k <= 1 else f"delayed rank-{k} updates")
+                               + (", fp32 products" if args.mixed else ", fp64"),
                    "n_impurities": n_imp, "L": L, "sweeps": 2200, "recompute_every": RECOMPUTE_EVERY,
-                   "proposals_per_step": proposals, "accept_rate": round(p_acc, 4)},
+                   "proposals_per_step": proposals, "accept_rate": round(p_acc, 4), "delay": k,
+                   "tile_rows_per_wave": rt, "graph": bool(args.graph)},
         "roofline": roofline,
+        "max_drift": max(r["max_drift"] for r in res),
     }
     if not args.no_single:
         single = single_impurity_rate(ctx, probs)

@@ -89,7 +89,11 @@ typedef struct {
     uint64_t site_id;           /* Philox key word 1 */
     int64_t sweep_offset;       /* added to the sweep index in the Philox counter */
     const int8_t *init_fields;  /* host, L entries (+1/-1), or NULL to draw them */
-    int32_t delay;              /* 0: library choice; 1: plain Sherman-Morrison */
+    int32_t delay;              /* 0: library choice (autotuned shape, else 1);
+                                   1: rank-one Sherman-Morrison updates;
+                                   2..32: delayed rank-k updates, flushed into G
+                                   every k accepted flips (fp32 products when
+                                   the context precision is HFQMC_MIXED) */
 } hfqmc_problem;
 
 /* Result of one impurity.  Pointer members are caller-owned and may be NULL. */
@@ -143,9 +147,37 @@ hfqmc_status hfqmc_stage(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t 
 hfqmc_status hfqmc_run(hfqmc_ctx *ctx);
 hfqmc_status hfqmc_collect(hfqmc_ctx *ctx, hfqmc_result *out);
 
-/* Device time in milliseconds of the sweep kernels of the last hfqmc_run,
- * from HIP events recorded on the context stream around them. */
+/* Same pass as hfqmc_run, replayed from a hipGraph captured on the first
+ * call after each hfqmc_stage (kernel classes are graph branches that run
+ * concurrently; the pass contains no memset and no host copy).  Results are
+ * identical to hfqmc_run. */
+hfqmc_status hfqmc_run_graph(hfqmc_ctx *ctx);
+
+/* Device time in milliseconds of the whole last pass (hfqmc_run or
+ * hfqmc_run_graph), from HIP events recorded on the context stream around
+ * it; *n_launches receives the number of kernel classes. */
 hfqmc_status hfqmc_last_run_ms(hfqmc_ctx *ctx, double *sweep_ms, int32_t *n_launches);
+
+/* Duration of class kernel i of the last eager hfqmc_run, from HIP events
+ * recorded on the stream it ran on, with its padded slice count and item
+ * count (pointers may be NULL).  Classes run largest L first, concurrently
+ * on up to four streams. */
+hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx *ctx, int32_t i, double *ms, int32_t *L_padded, int32_t *n_items);
+
+/* ---- autotuning (kernel shape per padded slice count) ----
+ * For every padded L present in `problems`, time each compiled kernel shape
+ * (tile-rows per wave; rank-one, or delayed with k in {4, 8, 16, 32} in the
+ * context precision) on those problems shortened to `sweeps` sweeps (>= 4),
+ * keep the fastest, and write the table to the context's tune cache (JSON,
+ * if a path was given to hfqmc_create).  Problems with delay 0 then use the
+ * tuned shape.  d_ws must hold hfqmc_workspace_size(problems); any staged
+ * batch is discarded (stage again). */
+hfqmc_status hfqmc_tune(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
+                        int32_t sweeps);
+/* The shape a problem with L slices and this delay would run with:
+ * tile-rows per wave, delay depth (1 = rank-one) and the tuned rate in
+ * proposals/s (0 if untuned).  Pointers may be NULL. */
+hfqmc_status hfqmc_plan(hfqmc_ctx *ctx, int32_t L, int32_t delay, int32_t *rt, int32_t *k, double *tuned_rate);
 
 /* ---- device-resident sites (state kept across DMFT iterations) ---- */
 
@@ -170,6 +202,44 @@ hfqmc_status hfqmc_site_force_flips(hfqmc_ctx *ctx, hfqmc_site *site, const int3
 hfqmc_status hfqmc_site_get_green(hfqmc_ctx *ctx, hfqmc_site *site, int32_t spin, double *LxL_row_major);
 hfqmc_status hfqmc_site_get_fields(hfqmc_ctx *ctx, hfqmc_site *site, int8_t *fields);
 hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drift);
+
+/* ---- serving: continuous batching of impurity solves on sites ----
+ * A library thread admits submitted requests while the CU shares of the
+ * admitted ones (1 / resident workgroups per CU of the site's kernel) fit
+ * the capacity, and advances every admitted request in launches of about
+ * `quantum_proposals` proposals each; requests that arrive while others run
+ * start in the next free launch slot, and launches of different kernel
+ * classes run concurrently.  Field and G state stay on the device: a request
+ * without init_fields on a site that already ran starts from the site's last
+ * fields with a fresh Dyson solve (the next DMFT iteration), otherwise from
+ * init_fields or drawn fields.  A request's result is bitwise the result of
+ * hfqmc_solve on the same problem, whatever else runs beside it.  Serving
+ * uses rank-one updates (delay 0 or 1).  The site must not be used by the
+ * test hooks while it has a request (EAGAIN). */
+
+/* quantum_proposals >= 1 (default 16384); capacity_cus > 0 sets the
+ * admission capacity in CUs (default: all CUs), 0 keeps the default. */
+hfqmc_status hfqmc_serve_config(hfqmc_ctx *ctx, int64_t quantum_proposals, double capacity_cus);
+/* Queue a request on a site (problem L and n_bins must match the site's).
+ * Inputs are copied before the call returns.  EAGAIN: the site has a
+ * request in progress, or the queue is full.  *ticket identifies it. */
+hfqmc_status hfqmc_submit(hfqmc_ctx *ctx, hfqmc_site *site, const hfqmc_problem *problem, uint64_t *ticket);
+/* EAGAIN while the request runs; OK (or its error status) once done, with
+ * `out` filled like hfqmc_collect does; the ticket is then released.
+ * ENOTFOUND: unknown, released or cancelled ticket. */
+hfqmc_status hfqmc_poll(hfqmc_ctx *ctx, uint64_t ticket, hfqmc_result *out);
+/* Drop a request (queued: at once; running: when its launch ends).  The
+ * site keeps the fields of its last completed launch. */
+hfqmc_status hfqmc_cancel(hfqmc_ctx *ctx, uint64_t ticket);
+
+typedef struct {
+    int64_t submitted, completed, cancelled, launches;
+    int32_t pending;        /* queued, not admitted */
+    int32_t active;         /* admitted, waiting for or in a launch */
+    double capacity_used;   /* CU shares held by admitted requests */
+    double capacity;
+} hfqmc_serve_stats_t;
+hfqmc_status hfqmc_serve_stats(hfqmc_ctx *ctx, hfqmc_serve_stats_t *out);
 
 #ifdef __cplusplus
 }

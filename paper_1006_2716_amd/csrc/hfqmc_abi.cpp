@@ -1,19 +1,31 @@
 // hfqmc_abi.cpp -- host side of the C ABI declared in include/hfqmc.h.
 //
 // Validates problems, computes the HS coupling, plans the batch (one kernel
-// class per padded slice count), lays out the caller's workspace, launches
-// the gfx950 kernels on the context stream and finalises bin statistics.
+// class per padded slice count and update kind), lays out the caller's
+// workspace, launches the gfx950 kernels (classes concurrently on forked
+// streams, optionally replayed from a captured hipGraph), autotunes the
+// kernel shape per class, finalises bin statistics, and runs the serving
+// engine: a host thread that admits impurity-solve requests on
+// device-resident sites and advances them in short launches (continuous
+// batching).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdarg>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hfqmc.h"
@@ -22,6 +34,7 @@
 namespace hfqmc {
 struct KernelInfo;
 const KernelInfo* find_kernel(int LT, int RT, int DK);
+int kernel_variants(int LT, int DK, int* rt_out, int max);
 int kernel_threads(const KernelInfo* k);
 size_t kernel_lds(const KernelInfo* k);
 hipError_t kernel_occupancy(const KernelInfo* k, int* blocks_per_cu);
@@ -53,26 +66,32 @@ hfqmc_status fail(hfqmc_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(HFQMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
   } while (0)
 
+#define TRY(expr)                        \
+  do {                                   \
+    hfqmc_status s_ = (expr);            \
+    if (s_ != HFQMC_OK) return s_;       \
+  } while (0)
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
-// Tile-rows per wave for a padded slice count and update kind (environment
-// override for tuning experiments).
-int choose_rt(int LT, int DK = 0) {
-  const char* e = getenv("HFQMC_RT");
-  if (e && DK == 0) {
-    int rt = strcmp(e, "max") == 0 ? LT / 16 : atoi(e);
-    if (find_kernel(LT, rt, 0)) return rt;
-  }
-  return LT == 64 ? 2 : 1;
-}
+constexpr int kMaxDelay = 32;    // panel capacity of the delayed-update kernels
+constexpr int kAuxStreams = 3;   // extra streams for concurrent kernel classes
+constexpr int kSrvStreams = 6;   // serving launch streams
 
-// Update kind of a problem: 0 plain rank-one, 1 delayed fp64, 2 delayed mixed.
-int update_kind(const hfqmc_problem& p, hfqmc_precision prec) {
-  const int k = p.delay == 0 ? 1 : p.delay;
-  if (k <= 1) return 0;
-  return prec == HFQMC_MIXED ? 2 : 1;
+// Kernel shape of one class: tile-rows per wave, update kind (0 plain
+// rank-one, 1 delayed fp64, 2 delayed mixed) and delay depth.
+struct Plan {
+  int rt = 1, dk = 0, k = 1;
+};
+
+// Untuned default tile-rows per wave (measured best on the L = 64 batch; 1
+// wherever only that variant exists).
+int default_rt(int LT, int dk) {
+  if (LT == 64) return 2;
+  (void)dk;
+  return 1;
 }
 
 // HS coupling from cosh(lambda) = exp(dtau U / 2), written as
@@ -90,7 +109,7 @@ hfqmc_status validate(const hfqmc_problem& p, int idx) {
   if (p.n_measure < p.n_bins) return fail(HFQMC_EINVAL, "problem %d: n_measure < n_bins", idx);
   if (p.n_warmup < 0) return fail(HFQMC_EINVAL, "problem %d: n_warmup < 0", idx);
   if (p.recompute_every < 1) return fail(HFQMC_EINVAL, "problem %d: recompute_every < 1", idx);
-  if (p.delay < 0) return fail(HFQMC_EINVAL, "problem %d: delay < 0", idx);
+  if (p.delay < 0 || p.delay > kMaxDelay) return fail(HFQMC_EINVAL, "problem %d: delay outside [0,%d]", idx, kMaxDelay);
   for (int s = 0; s < 2; ++s) {
     if (!p.weiss[s]) return fail(HFQMC_EINVAL, "problem %d: weiss[%d] is NULL", idx, s);
     for (int k = 0; k < p.L; ++k)
@@ -123,7 +142,7 @@ void fill_constants(ImpDesc& d, const hfqmc_problem& p) {
   d.rng_offset = p.sweep_offset;
   d.seed = p.seed;
   d.site = p.site_id;
-  d.delay = p.delay == 0 ? 1 : p.delay;
+  d.delay = 1;
 }
 
 // Bin counts, means and errors from per-bin sums.
@@ -189,13 +208,14 @@ void tiles_to_rowmajor(const double* st, int L, int LT, int RT, int spin, double
 
 struct Group {
   const KernelInfo* k;
+  int LT, rt, dk;
   int first, count, grid;
 };
 
 // Workspace layout of one batch.
 struct Layout {
-  size_t descs, order, queues, weiss, fields, status, bins, state, total;
-  std::vector<size_t> w_off, f_off, b_off, s_off;
+  size_t descs, order, queues, weiss, init, fields, status, bins, state, total;
+  std::vector<size_t> w_off, i_off, f_off, b_off, s_off;
 };
 
 Layout plan_layout(const hfqmc_problem* p, int n) {
@@ -212,6 +232,13 @@ Layout plan_layout(const hfqmc_problem* p, int n) {
   for (int i = 0; i < n; ++i) {
     lo.w_off[i] = off;
     off += sizeof(double) * 2 * p[i].L;
+  }
+  off = align_up(off, 256);
+  lo.init = off;
+  lo.i_off.resize(n);
+  for (int i = 0; i < n; ++i) {
+    lo.i_off[i] = off;
+    off += align_up(p[i].L, 8);
   }
   off = align_up(off, 256);
   lo.fields = off;
@@ -245,15 +272,149 @@ struct PoolBlock {
   size_t off, bytes;
 };
 
+// Autotune cache entry: best shape for one padded slice count.
+struct TuneEntry {
+  std::string prec;
+  int LT, rt, k;
+  double rate;
+};
+
+const char* prec_name(hfqmc_precision p) { return p == HFQMC_MIXED ? "mixed" : "fp64"; }
+
+// ---- minimal reader for the cache file this library writes ----
+bool json_find_num(const std::string& obj, const char* key, double* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t pos = obj.find(k);
+  if (pos == std::string::npos) return false;
+  pos = obj.find(':', pos + k.size());
+  if (pos == std::string::npos) return false;
+  const char* b = obj.c_str() + pos + 1;
+  char* e = nullptr;
+  *v = std::strtod(b, &e);
+  return e != b;
+}
+
+bool json_find_str(const std::string& obj, const char* key, std::string* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t pos = obj.find(k);
+  if (pos == std::string::npos) return false;
+  pos = obj.find(':', pos + k.size());
+  if (pos == std::string::npos) return false;
+  const size_t q0 = obj.find('"', pos + 1);
+  if (q0 == std::string::npos) return false;
+  const size_t q1 = obj.find('"', q0 + 1);
+  if (q1 == std::string::npos) return false;
+  *v = obj.substr(q0 + 1, q1 - q0 - 1);
+  return true;
+}
+
+std::vector<TuneEntry> read_tune_cache(const std::string& path) {
+  std::vector<TuneEntry> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  std::string arch;
+  if (!json_find_str(text, "arch", &arch) || arch != "gfx950") return out;
+  size_t pos = text.find("\"entries\"");
+  if (pos == std::string::npos) return out;
+  pos = text.find('[', pos);
+  while (pos != std::string::npos) {
+    const size_t b = text.find('{', pos), e = b == std::string::npos ? b : text.find('}', b);
+    if (b == std::string::npos || e == std::string::npos) break;
+    const std::string obj = text.substr(b, e - b + 1);
+    TuneEntry t;
+    double LT, rt, k, rate = 0;
+    if (json_find_str(obj, "precision", &t.prec) && json_find_num(obj, "L_padded", &LT) &&
+        json_find_num(obj, "rt", &rt) && json_find_num(obj, "k", &k)) {
+      json_find_num(obj, "proposals_per_s", &rate);
+      t.LT = (int)LT;
+      t.rt = (int)rt;
+      t.k = (int)k;
+      t.rate = rate;
+      out.push_back(t);
+    }
+    pos = e + 1;
+  }
+  return out;
+}
+
+bool write_tune_cache(const std::string& path, const std::vector<TuneEntry>& v) {
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
+  for (size_t i = 0; i < v.size(); ++i)
+    std::fprintf(f, "  {\"precision\": \"%s\", \"L_padded\": %d, \"rt\": %d, \"k\": %d, \"proposals_per_s\": %.6g}%s\n",
+                 v[i].prec.c_str(), v[i].LT, v[i].rt, v[i].k, v[i].rate, i + 1 < v.size() ? "," : "");
+  std::fprintf(f, "]}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
 }  // namespace
+
+// ------------------------------------------------------------- sites & serving
 
 struct hfqmc_site {
   int L, LT, RT, n_bins;
   size_t off, bytes;  // pool block
-  size_t o_desc, o_weiss, o_fields, o_bins, o_status, o_state, o_force;
+  size_t o_desc, o_weiss, o_init, o_fields, o_bins, o_status, o_state, o_force, o_queue;
   bool defined = false, has_state = false;
+  bool busy = false;  // a serving request owns the site (guarded by the server mutex)
   hfqmc_problem prob{};
 };
+
+namespace {
+
+enum ReqState { R_PENDING, R_READY, R_INFLIGHT, R_DONE };
+
+struct Request {
+  uint64_t ticket = 0;
+  hfqmc_site* site = nullptr;
+  hfqmc_problem prob{};
+  int64_t total = 0, done = 0, q = 0;
+  int state = R_PENDING;
+  bool first = true, given = false, keep = false, cancel = false;
+  double weight = 0.0;
+  hfqmc_status status = HFQMC_OK;
+  std::vector<double> g[2], gerr[2], bins;
+  std::vector<int8_t> fields;
+  hfqmc_result res{};
+};
+
+struct Launch {
+  int slot;
+  std::vector<Request*> items;
+};
+
+struct Server {
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool started = false, stop = false, failed = false;
+  std::string error;
+  std::deque<Request*> pending;
+  std::vector<Request*> ready;
+  std::vector<Launch> inflight;
+  std::map<uint64_t, Request*> tickets;
+  uint64_t next_ticket = 1;
+  double used = 0.0;
+  double capacity = 0.0;      // CU shares available to admitted requests
+  int64_t quantum = 16384;    // proposals per request per launch
+  int max_items = 2048;       // requests per launch
+  size_t max_pending = 1 << 16;
+  hipStream_t streams[kSrvStreams] = {};
+  hipEvent_t events[kSrvStreams] = {};
+  bool slot_busy[kSrvStreams] = {};
+  hipStream_t io = nullptr;
+  size_t area_off = 0, area_bytes = 0, slot_bytes = 0;
+  uint8_t* host_img[kSrvStreams] = {};
+  int64_t submitted = 0, completed = 0, cancelled = 0, launches = 0;
+};
+
+}  // namespace
 
 struct hfqmc_ctx {
   int device = 0;
@@ -263,28 +424,47 @@ struct hfqmc_ctx {
   std::mutex mu;
   // staged batch
   bool staged = false;
-  bool fields_given = false;
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
   std::vector<hfqmc_problem> probs;
   std::vector<Group> groups;
   Layout lo;
-  std::vector<uint8_t> host_in;   // image of descs..fields
-  std::vector<uint8_t> host_out;  // image of fields..bins end
-  std::vector<hipEvent_t> ev;
+  hipStream_t aux[kAuxStreams] = {};
+  hipStream_t cap = nullptr;  // capture stream for the graph
+  hipEvent_t ev_fork = nullptr, ev_join[kAuxStreams] = {}, ev_start = nullptr, ev_end = nullptr;
+  std::vector<hipEvent_t> ev;  // per group start/end
+  hipGraphExec_t gexec = nullptr;
   int last_launches = 0;
+  bool last_timed_groups = false;
+  // tuning
+  std::string tune_path;
+  std::vector<TuneEntry> tune_all;  // every entry of the cache file
+  std::map<int, TuneEntry> tune;    // this precision, by padded L
   // pool
   uint8_t* pool = nullptr;
   size_t pool_bytes = 0;
   std::vector<PoolBlock> free_list;
   std::vector<hfqmc_site*> sites;
-  std::string err;
+  Server srv;
 };
 
 namespace {
 
 hfqmc_status set_device(hfqmc_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
+  return HFQMC_OK;
+}
+
+hfqmc_status ensure_streams(hfqmc_ctx* c) {
+  if (c->ev_start) return HFQMC_OK;
+  for (int a = 0; a < kAuxStreams; ++a) {
+    HIP_TRY(hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_join[a], hipEventDisableTiming));
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreate(&c->ev_end));
+  HIP_TRY(hipEventCreate(&c->ev_start));
   return HFQMC_OK;
 }
 
@@ -326,12 +506,160 @@ void pool_free(hfqmc_ctx* c, size_t off, size_t bytes) {
   c->free_list.swap(merged);
 }
 
+// Kernel shape for a problem: explicit delay, else the tuned entry of its
+// class, else the default plain kernel.
+Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
+  const int LT = padded_L(p.L);
+  const int dk_delayed = c->prec == HFQMC_MIXED ? 2 : 1;
+  Plan pl;
+  auto it = c->tune.find(LT);
+  const bool tuned = it != c->tune.end();
+  if (p.delay == 0 && tuned) {
+    pl.k = it->second.k;
+    pl.dk = pl.k > 1 ? dk_delayed : 0;
+    pl.rt = it->second.rt;
+  } else if (p.delay <= 1) {
+    pl.rt = tuned && it->second.k == 1 ? it->second.rt : default_rt(LT, 0);
+  } else {
+    pl.k = p.delay;
+    pl.dk = dk_delayed;
+    pl.rt = tuned && it->second.k > 1 ? it->second.rt : default_rt(LT, pl.dk);
+  }
+  return pl;
+}
+
+// Stage a batch: group by kernel class (padded L, shape), order items inside
+// a class by descending work, upload descriptors and inputs.  `force`, when
+// set, overrides the plan of every problem (autotuning).
+hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws, size_t ws_bytes, const Plan* force) {
+  for (int i = 0; i < n; ++i) TRY(validate(p[i], i));
+  Layout lo = plan_layout(p, n);
+  if (ws_bytes < lo.total) return fail(HFQMC_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, lo.total);
+  TRY(set_device(c));
+  TRY(ensure_streams(c));
+  if (c->gexec) {
+    HIP_TRY(hipGraphExecDestroy(c->gexec));
+    c->gexec = nullptr;
+  }
+  c->staged = false;
+
+  std::vector<int> idx(n);
+  std::vector<Plan> plan(n);
+  for (int i = 0; i < n; ++i) {
+    idx[i] = i;
+    plan[i] = force ? *force : plan_for(c, p[i]);
+    if (!find_kernel(padded_L(p[i].L), plan[i].rt, plan[i].dk))
+      return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", i, plan[i].dk ? "delayed-update" : "sweep",
+                  p[i].L);
+  }
+  auto cost = [&](int i) { return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * p[i].L; };
+  auto key = [&](int i) { return std::make_tuple(-padded_L(p[i].L), plan[i].dk, plan[i].rt); };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (key(a) != key(b)) return key(a) < key(b);
+    return cost(a) > cost(b);
+  });
+  std::vector<Group> groups;
+  for (int k = 0; k < n;) {
+    int e = k;
+    while (e < n && key(idx[e]) == key(idx[k])) ++e;
+    const int LT = padded_L(p[idx[k]].L);
+    const Plan& pl = plan[idx[k]];
+    const KernelInfo* ki = find_kernel(LT, pl.rt, pl.dk);
+    int bpc = 0;
+    HIP_TRY(kernel_occupancy(ki, &bpc));
+    if (bpc < 1) return fail(HFQMC_EDEVICE, "kernel for L=%d does not fit on a CU", LT);
+    groups.push_back({ki, LT, pl.rt, pl.dk, k, e - k, std::min(e - k, bpc * c->n_cu)});
+    k = e;
+  }
+  if (groups.size() > 64) return fail(HFQMC_EINVAL, "too many kernel classes");
+
+  // host image of the input region [descs, status)
+  std::vector<uint8_t> img(lo.status, 0);
+  ImpDesc* descs = reinterpret_cast<ImpDesc*>(img.data() + lo.descs);
+  int32_t* order = reinterpret_cast<int32_t*>(img.data() + lo.order);
+  for (int i = 0; i < n; ++i) {
+    ImpDesc d{};
+    fill_constants(d, p[i]);
+    d.LT = padded_L(p[i].L);
+    d.op = OP_SWEEPS;
+    d.delay = plan[i].k;
+    d.flags = F_ZERO_ACC | (p[i].init_fields ? F_FIELDS_GIVEN : 0) | F_SAVE;
+    d.off_weiss = (int64_t)lo.w_off[i];
+    d.off_init = (int64_t)lo.i_off[i];
+    d.off_fields = (int64_t)lo.f_off[i];
+    d.off_bins = (int64_t)lo.b_off[i];
+    d.off_status = (int64_t)(lo.status + sizeof(ImpStatus) * i);
+    d.off_state = (int64_t)lo.s_off[i];
+    d.off_force = 0;
+    descs[i] = d;
+    std::memcpy(img.data() + lo.w_off[i], p[i].weiss[0], sizeof(double) * p[i].L);
+    std::memcpy(img.data() + lo.w_off[i] + sizeof(double) * p[i].L, p[i].weiss[1], sizeof(double) * p[i].L);
+    if (p[i].init_fields) std::memcpy(img.data() + lo.i_off[i], p[i].init_fields, p[i].L);
+  }
+  for (int i = 0; i < n; ++i) order[i] = idx[i];
+  c->ws = reinterpret_cast<uint8_t*>(d_ws);
+  c->ws_bytes = ws_bytes;
+  HIP_TRY(hipMemcpyAsync(c->ws, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->probs.assign(p, p + n);
+  for (auto& q : c->probs) q.weiss[0] = q.weiss[1] = nullptr, q.init_fields = nullptr;
+  c->groups = groups;
+  c->lo = lo;
+  c->staged = true;
+  return HFQMC_OK;
+}
+
+// Enqueue one whole pass on `main`: reset the work queues, then every class
+// kernel, classes spread over the auxiliary streams so that they run
+// concurrently (fork/join through events; valid under stream capture).  No
+// memset and no host copy: the pass can be captured into a graph.
+hfqmc_status enqueue_pass(hfqmc_ctx* c, hipStream_t main, bool timing) {
+  const int G = (int)c->groups.size();
+  const int ns = std::min(G, 1 + kAuxStreams);
+  if (timing) TRY(ensure_events(c, 2 * (size_t)G));
+  HIP_TRY(launch_zero(c->ws + c->lo.queues, sizeof(int32_t) * 64, main));
+  if (ns > 1) {
+    HIP_TRY(hipEventRecord(c->ev_fork, main));
+    for (int a = 0; a < ns - 1; ++a) HIP_TRY(hipStreamWaitEvent(c->aux[a], c->ev_fork, 0));
+  }
+  const ImpDesc* descs = reinterpret_cast<const ImpDesc*>(c->ws + c->lo.descs);
+  const int32_t* order = reinterpret_cast<const int32_t*>(c->ws + c->lo.order);
+  int* queues = reinterpret_cast<int*>(c->ws + c->lo.queues);
+  for (int gi = 0; gi < G; ++gi) {
+    const Group& gr = c->groups[gi];
+    hipStream_t st = gi % ns == 0 ? main : c->aux[gi % ns - 1];
+    if (timing) HIP_TRY(hipEventRecord(c->ev[2 * gi], st));
+    HIP_TRY(launch_sweep(gr.k, gr.grid, st, descs, order + gr.first, gr.count, queues + gi, c->ws));
+    if (timing) HIP_TRY(hipEventRecord(c->ev[2 * gi + 1], st));
+  }
+  if (ns > 1) {
+    for (int a = 0; a < ns - 1; ++a) {
+      HIP_TRY(hipEventRecord(c->ev_join[a], c->aux[a]));
+      HIP_TRY(hipStreamWaitEvent(main, c->ev_join[a], 0));
+    }
+  }
+  return HFQMC_OK;
+}
+
+// Per-pass device time (ms) from the start/end events on the context stream.
+hfqmc_status pass_ms(hfqmc_ctx* c, double* ms) {
+  HIP_TRY(hipEventSynchronize(c->ev_end));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev_start, c->ev_end));
+  *ms = t;
+  return HFQMC_OK;
+}
+
+// ---- serving helpers (the server mutex is held by the caller) ----
+
 size_t site_layout(hfqmc_site* s) {
   size_t off = 0;
   s->o_desc = off;
   off = align_up(off + sizeof(ImpDesc), 256);
   s->o_weiss = off;
   off = align_up(off + sizeof(double) * 2 * s->L, 256);
+  s->o_init = off;
+  off = align_up(off + s->L, 256);
   s->o_fields = off;
   off = align_up(off + s->L, 256);
   s->o_status = off;
@@ -342,34 +670,274 @@ size_t site_layout(hfqmc_site* s) {
   off = align_up(off + sizeof(double) * 2 * (size_t)s->LT * s->LT, 256);
   s->o_force = off;
   off = align_up(off + 1024 * (sizeof(int32_t) + sizeof(double)), 256);
-  // queue counter + order entry
+  s->o_queue = off;  // queue counter + order entry
   off = align_up(off + 256, 256);
   return off;
 }
 
-// Launch one work item on a site (blocking).
+void site_offsets(const hfqmc_site* s, ImpDesc& d) {
+  d.off_weiss = (int64_t)(s->off + s->o_weiss);
+  d.off_init = (int64_t)(s->off + s->o_init);
+  d.off_fields = (int64_t)(s->off + s->o_fields);
+  d.off_bins = (int64_t)(s->off + s->o_bins);
+  d.off_status = (int64_t)(s->off + s->o_status);
+  d.off_state = (int64_t)(s->off + s->o_state);
+  d.off_force = (int64_t)(s->off + s->o_force);
+  d.LT = s->LT;
+}
+
+// Launch one work item on a site (blocking, context stream).
 hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d) {
   uint8_t* base = c->pool + s->off;
-  d.off_weiss = (int64_t)s->o_weiss;
-  d.off_fields = (int64_t)s->o_fields;
-  d.off_bins = (int64_t)s->o_bins;
-  d.off_status = (int64_t)s->o_status;
-  d.off_state = (int64_t)s->o_state;
-  d.off_force = (int64_t)s->o_force;
-  d.LT = s->LT;
+  site_offsets(s, d);
   const KernelInfo* k = find_kernel(s->LT, s->RT, 0);
   if (!k) return fail(HFQMC_EINVAL, "no kernel for LT=%d RT=%d", s->LT, s->RT);
-  const size_t qoff = s->o_force + align_up(1024 * (sizeof(int32_t) + sizeof(double)), 256);
   struct {
     int32_t queue, order;
   } qo = {0, 0};
   HIP_TRY(hipMemcpyAsync(base + s->o_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(base + qoff, &qo, sizeof qo, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(base + s->o_queue, &qo, sizeof qo, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(launch_sweep(k, 1, c->stream, reinterpret_cast<const ImpDesc*>(base + s->o_desc),
-                       reinterpret_cast<const int32_t*>(base + qoff + 4), 1, reinterpret_cast<int*>(base + qoff),
-                       base));
+                       reinterpret_cast<const int32_t*>(base + s->o_queue + 4), 1,
+                       reinterpret_cast<int*>(base + s->o_queue), c->pool));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return HFQMC_OK;
+}
+
+// Blocks per CU of a site's kernel (its admission weight is 1 / that).
+int site_bpc(const hfqmc_site* s) {
+  const KernelInfo* k = find_kernel(s->LT, s->RT, 0);
+  int bpc = 0;
+  if (!k || kernel_occupancy(k, &bpc) != hipSuccess || bpc < 1) return 1;
+  return bpc;
+}
+
+// Copy a finished request's bins, status and fields back and finalise them.
+hfqmc_status srv_finish(hfqmc_ctx* c, Request* r) {
+  Server& S = c->srv;
+  hfqmc_site* s = r->site;
+  const int L = s->L, NV = n_values(L);
+  std::vector<double> sums((size_t)s->n_bins * NV);
+  ImpStatus st{};
+  r->fields.resize(L);
+  uint8_t* base = c->pool + s->off;
+  HIP_TRY(hipMemcpyAsync(sums.data(), base + s->o_bins, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, S.io));
+  HIP_TRY(hipMemcpyAsync(&st, base + s->o_status, sizeof st, hipMemcpyDeviceToHost, S.io));
+  HIP_TRY(hipMemcpyAsync(r->fields.data(), base + s->o_fields, L, hipMemcpyDeviceToHost, S.io));
+  HIP_TRY(hipStreamSynchronize(S.io));
+  for (int k = 0; k < 2; ++k) {
+    r->g[k].assign(L + 1, 0.0);
+    r->gerr[k].assign(L + 1, 0.0);
+    r->res.g[k] = r->g[k].data();
+    r->res.g_err[k] = r->gerr[k].data();
+  }
+  r->bins.assign(sums.size(), 0.0);
+  r->res.bins = r->bins.data();
+  r->res.final_fields = nullptr;
+  finalise(r->prob, sums.data(), st, r->fields.data(), r->res);
+  r->status = (hfqmc_status)r->res.status;
+  return HFQMC_OK;
+}
+
+// One pass of the engine: retire finished launches, admit, launch.  Returns
+// true when anything is in flight.
+bool srv_step(hfqmc_ctx* c) {
+  Server& S = c->srv;
+  auto device_fail = [&](const char* what, hipError_t e) {
+    S.failed = true;
+    S.error = std::string(what) + ": " + hipGetErrorString(e);
+  };
+  // 1. retire
+  for (size_t i = 0; i < S.inflight.size();) {
+    Launch& L = S.inflight[i];
+    const hipError_t q = hipEventQuery(S.events[L.slot]);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    if (q != hipSuccess) device_fail("hipEventQuery", q);
+    for (Request* r : L.items) {
+      r->done += r->q;
+      r->first = false;
+      r->q = 0;
+      if (r->cancel) {
+        S.used -= r->weight;
+        r->site->busy = false;
+        r->site->has_state = true;
+        S.tickets.erase(r->ticket);
+        ++S.cancelled;
+        delete r;
+      } else if (S.failed || r->done >= r->total) {
+        S.used -= r->weight;
+        if (S.failed) {
+          r->status = HFQMC_EDEVICE;
+        } else if (srv_finish(c, r) != HFQMC_OK) {
+          S.failed = true;
+          S.error = t_err;
+          r->status = HFQMC_EDEVICE;
+        }
+        r->state = R_DONE;
+        r->site->busy = false;
+        r->site->has_state = true;
+        ++S.completed;
+      } else {
+        r->state = R_READY;
+        S.ready.push_back(r);
+      }
+    }
+    S.slot_busy[L.slot] = false;
+    S.inflight.erase(S.inflight.begin() + i);
+  }
+  if (S.failed) {
+    for (Request* r : S.ready) {
+      S.used -= r->weight;
+      r->status = HFQMC_EDEVICE;
+      r->state = R_DONE;
+      r->site->busy = false;
+    }
+    S.ready.clear();
+    return !S.inflight.empty();
+  }
+  if (S.stop) return !S.inflight.empty();
+  // 2. admit in arrival order; a request that does not fit lets smaller
+  // later ones pass
+  for (auto it = S.pending.begin(); it != S.pending.end();) {
+    Request* r = *it;
+    if (S.used + r->weight <= S.capacity + 1e-9 || S.used <= 1e-9) {
+      S.used += r->weight;
+      r->state = R_READY;
+      S.ready.push_back(r);
+      it = S.pending.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  // 3. launch: one kernel class per free stream, its ready requests together
+  while (!S.ready.empty()) {
+    int slot = -1;
+    for (int k = 0; k < kSrvStreams; ++k)
+      if (!S.slot_busy[k]) {
+        slot = k;
+        break;
+      }
+    if (slot < 0) break;
+    const int LT = S.ready.front()->site->LT, RT = S.ready.front()->site->RT;
+    Launch L{slot, {}};
+    for (auto it = S.ready.begin(); it != S.ready.end() && (int)L.items.size() < S.max_items;) {
+      if ((*it)->site->LT == LT && (*it)->site->RT == RT) {
+        L.items.push_back(*it);
+        it = S.ready.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    const int n = (int)L.items.size();
+    uint8_t* img = S.host_img[slot];
+    ImpDesc* descs = reinterpret_cast<ImpDesc*>(img);
+    int32_t* order = reinterpret_cast<int32_t*>(img + align_up(sizeof(ImpDesc) * S.max_items, 256));
+    int32_t* queue = order + S.max_items;
+    for (int i = 0; i < n; ++i) {
+      Request* r = L.items[i];
+      ImpDesc d{};
+      fill_constants(d, r->prob);
+      site_offsets(r->site, d);
+      d.op = OP_SWEEPS;
+      d.delay = 1;
+      const int64_t q = std::max<int64_t>(1, S.quantum / r->site->L);
+      r->q = std::min(q, r->total - r->done);
+      d.sweep_begin = r->done;
+      d.sweep_end = r->done + r->q;
+      if (r->first)
+        d.flags = F_ZERO_ACC | F_SAVE | (r->given ? F_FIELDS_GIVEN : (r->keep ? F_KEEP_FIELDS : 0));
+      else
+        d.flags = F_RESUME | F_SAVE;
+      descs[i] = d;
+      order[i] = i;
+      r->state = R_INFLIGHT;
+    }
+    *queue = 0;
+    uint8_t* dev = c->pool + S.area_off + (size_t)slot * S.slot_bytes;
+    const size_t bytes = reinterpret_cast<uint8_t*>(queue + 1) - img;
+    const KernelInfo* k = find_kernel(LT, RT, 0);
+    int bpc = 1;
+    hipError_t e = kernel_occupancy(k, &bpc);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev, img, bytes, hipMemcpyHostToDevice, S.streams[slot]);
+    if (e == hipSuccess)
+      e = launch_sweep(k, std::min(n, std::max(1, bpc) * c->n_cu), S.streams[slot], reinterpret_cast<const ImpDesc*>(dev),
+                       reinterpret_cast<const int32_t*>(dev + (reinterpret_cast<uint8_t*>(order) - img)), n,
+                       reinterpret_cast<int*>(dev + (reinterpret_cast<uint8_t*>(queue) - img)), c->pool);
+    if (e == hipSuccess) e = hipEventRecord(S.events[slot], S.streams[slot]);
+    if (e != hipSuccess) device_fail("serving launch", e);
+    S.slot_busy[slot] = true;
+    S.inflight.push_back(std::move(L));
+    ++S.launches;
+  }
+  return !S.inflight.empty();
+}
+
+void srv_main(hfqmc_ctx* c) {
+  Server& S = c->srv;
+  (void)hipSetDevice(c->device);
+  std::unique_lock<std::mutex> lk(S.mu);
+  for (;;) {
+    const bool busy = srv_step(c);
+    if (S.stop && !busy) break;
+    if (busy)
+      S.cv.wait_for(lk, std::chrono::microseconds(50));
+    else
+      S.cv.wait(lk, [&] { return S.stop || !S.pending.empty() || !S.ready.empty(); });
+  }
+}
+
+// Streams, pinned launch images and the device launch area (from the pool);
+// the context mutex is held.
+hfqmc_status srv_start(hfqmc_ctx* c) {
+  Server& S = c->srv;
+  if (S.started) return HFQMC_OK;
+  TRY(set_device(c));
+  S.slot_bytes = align_up(align_up(sizeof(ImpDesc) * S.max_items, 256) + sizeof(int32_t) * (S.max_items + 1), 256);
+  S.area_bytes = S.slot_bytes * kSrvStreams;
+  TRY(pool_alloc(c, S.area_bytes, &S.area_off));
+  for (int k = 0; k < kSrvStreams; ++k) {
+    HIP_TRY(hipStreamCreateWithFlags(&S.streams[k], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&S.events[k], hipEventDisableTiming));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S.host_img[k]), S.slot_bytes, hipHostMallocDefault));
+  }
+  HIP_TRY(hipStreamCreateWithFlags(&S.io, hipStreamNonBlocking));
+  if (S.capacity <= 0.0) S.capacity = (double)c->n_cu;
+  S.stop = false;
+  S.th = std::thread(srv_main, c);
+  S.started = true;
+  return HFQMC_OK;
+}
+
+void srv_shutdown(hfqmc_ctx* c) {
+  Server& S = c->srv;
+  if (!S.started) return;
+  {
+    std::lock_guard<std::mutex> g(S.mu);
+    S.stop = true;  // launches in flight drain, nothing new starts
+  }
+  S.cv.notify_all();
+  S.th.join();
+  for (auto& kv : S.tickets) delete kv.second;  // every live request holds a ticket
+  S.tickets.clear();
+  S.pending.clear();
+  S.ready.clear();
+  for (int k = 0; k < kSrvStreams; ++k) {
+    (void)hipStreamDestroy(S.streams[k]);
+    (void)hipEventDestroy(S.events[k]);
+    (void)hipHostFree(S.host_img[k]);
+  }
+  (void)hipStreamDestroy(S.io);
+  S.started = false;
+}
+
+bool site_known(hfqmc_ctx* c, hfqmc_site* s) { return std::find(c->sites.begin(), c->sites.end(), s) != c->sites.end(); }
+
+bool site_busy(hfqmc_ctx* c, hfqmc_site* s) {
+  std::lock_guard<std::mutex> g(c->srv.mu);
+  return s->busy;
 }
 
 }  // namespace
@@ -385,7 +953,6 @@ hfqmc_status hfqmc_lambda(double dtau, double U, double* lambda_out) {
 
 hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precision, const char* tune_cache,
                           hfqmc_ctx** out) {
-  (void)tune_cache;
   if (!out) return fail(HFQMC_EINVAL, "hfqmc_create: out is NULL");
   if (precision != HFQMC_FP64 && precision != HFQMC_MIXED) return fail(HFQMC_EINVAL, "bad precision");
   int ndev = 0;
@@ -408,6 +975,15 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     return fail(HFQMC_EDEVICE, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
   }
   c->n_cu = prop.multiProcessorCount;
+  if (tune_cache) {
+    c->tune_path = tune_cache;
+    c->tune_all = read_tune_cache(c->tune_path);
+    for (const auto& t : c->tune_all) {
+      const int dk = t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0;
+      if (t.prec == prec_name(precision) && t.k >= 1 && t.k <= kMaxDelay && find_kernel(t.LT, t.rt, dk))
+        c->tune[t.LT] = t;
+    }
+  }
   *out = c;
   return HFQMC_OK;
 }
@@ -415,7 +991,19 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
 void hfqmc_destroy(hfqmc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  srv_shutdown(c);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->ev_start) {
+    for (int a = 0; a < kAuxStreams; ++a) {
+      (void)hipStreamDestroy(c->aux[a]);
+      (void)hipEventDestroy(c->ev_join[a]);
+    }
+    (void)hipStreamDestroy(c->cap);
+    (void)hipEventDestroy(c->ev_fork);
+    (void)hipEventDestroy(c->ev_start);
+    (void)hipEventDestroy(c->ev_end);
+  }
   for (auto s : c->sites) delete s;
   delete c;
 }
@@ -424,10 +1012,7 @@ const char* hfqmc_last_error(const hfqmc_ctx*) { return t_err.c_str(); }
 
 hfqmc_status hfqmc_workspace_size(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, size_t* bytes) {
   if (!c || !bytes || n < 0 || (n > 0 && !p)) return fail(HFQMC_EINVAL, "hfqmc_workspace_size: bad arguments");
-  for (int i = 0; i < n; ++i) {
-    hfqmc_status s = validate(p[i], i);
-    if (s) return s;
-  }
+  for (int i = 0; i < n; ++i) TRY(validate(p[i], i));
   *bytes = plan_layout(p, n).total;
   return HFQMC_OK;
 }
@@ -435,105 +1020,44 @@ hfqmc_status hfqmc_workspace_size(hfqmc_ctx* c, const hfqmc_problem* p, int32_t 
 hfqmc_status hfqmc_stage(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d_ws, size_t ws_bytes) {
   if (!c || n < 1 || !p || !d_ws) return fail(HFQMC_EINVAL, "hfqmc_stage: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
-  for (int i = 0; i < n; ++i) {
-    hfqmc_status s = validate(p[i], i);
-    if (s) return s;
-  }
-  Layout lo = plan_layout(p, n);
-  if (ws_bytes < lo.total) return fail(HFQMC_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, lo.total);
-  if (hfqmc_status s = set_device(c)) return s;
-
-  // group items by kernel class (padded L, update kind); inside a class order
-  // items by descending work
-  std::vector<int> idx(n), kind(n);
-  for (int i = 0; i < n; ++i) {
-    idx[i] = i;
-    kind[i] = update_kind(p[i], c->prec);
-    if (kind[i] && !find_kernel(padded_L(p[i].L), choose_rt(padded_L(p[i].L), kind[i]), kind[i]))
-      return fail(HFQMC_EINVAL, "problem %d: no delayed-update kernel for L=%d", i, p[i].L);
-    if (p[i].delay > 32) return fail(HFQMC_EINVAL, "problem %d: delay %d > 32", i, p[i].delay);
-  }
-  auto cost = [&](int i) { return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * p[i].L; };
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-    const int la = padded_L(p[a].L), lb = padded_L(p[b].L);
-    if (la != lb) return la > lb;
-    if (kind[a] != kind[b]) return kind[a] < kind[b];
-    return cost(a) > cost(b);
-  });
-  std::vector<Group> groups;
-  for (int k = 0; k < n;) {
-    const int LT = padded_L(p[idx[k]].L), DK = kind[idx[k]];
-    int e = k;
-    while (e < n && padded_L(p[idx[e]].L) == LT && kind[idx[e]] == DK) ++e;
-    const KernelInfo* ki = find_kernel(LT, choose_rt(LT, DK), DK);
-    if (!ki) return fail(HFQMC_EINVAL, "no kernel for padded L=%d", LT);
-    int bpc = 0;
-    HIP_TRY(kernel_occupancy(ki, &bpc));
-    if (bpc < 1) return fail(HFQMC_EDEVICE, "kernel for L=%d does not fit on a CU", LT);
-    const int grid = std::min(e - k, bpc * c->n_cu);
-    groups.push_back({ki, k, e - k, grid});
-    k = e;
-  }
-  if (groups.size() > 64) return fail(HFQMC_EINVAL, "too many kernel classes");
-
-  // host image of the input region [descs, fields end)
-  std::vector<uint8_t> img(lo.status, 0);
-  ImpDesc* descs = reinterpret_cast<ImpDesc*>(img.data() + lo.descs);
-  int32_t* order = reinterpret_cast<int32_t*>(img.data() + lo.order);
-  for (int i = 0; i < n; ++i) {
-    ImpDesc d{};
-    fill_constants(d, p[i]);
-    d.LT = padded_L(p[i].L);
-    d.op = OP_SWEEPS;
-    d.flags = F_ZERO_ACC | (p[i].init_fields ? F_FIELDS_GIVEN : 0) | F_SAVE;
-    d.off_weiss = (int64_t)lo.w_off[i];
-    d.off_fields = (int64_t)lo.f_off[i];
-    d.off_bins = (int64_t)lo.b_off[i];
-    d.off_status = (int64_t)(lo.status + sizeof(ImpStatus) * i);
-    d.off_state = (int64_t)lo.s_off[i];
-    d.off_force = 0;
-    descs[i] = d;
-    std::memcpy(img.data() + lo.w_off[i], p[i].weiss[0], sizeof(double) * p[i].L);
-    std::memcpy(img.data() + lo.w_off[i] + sizeof(double) * p[i].L, p[i].weiss[1], sizeof(double) * p[i].L);
-    if (p[i].init_fields) std::memcpy(img.data() + lo.f_off[i], p[i].init_fields, p[i].L);
-  }
-  for (int i = 0; i < n; ++i) order[i] = idx[i];
-  c->ws = reinterpret_cast<uint8_t*>(d_ws);
-  c->ws_bytes = ws_bytes;
-  HIP_TRY(hipMemcpyAsync(c->ws, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  c->probs.assign(p, p + n);
-  c->groups = groups;
-  c->lo = lo;
-  c->host_in.swap(img);
-  c->fields_given = false;
-  for (int i = 0; i < n; ++i) c->fields_given |= p[i].init_fields != nullptr;
-  c->staged = true;
-  return HFQMC_OK;
+  return stage_impl(c, p, n, d_ws, ws_bytes, nullptr);
 }
 
 hfqmc_status hfqmc_run(hfqmc_ctx* c) {
   if (!c || !c->staged) return fail(HFQMC_EINVAL, "hfqmc_run: nothing staged");
   std::lock_guard<std::mutex> g(c->mu);
-  if (hfqmc_status s = set_device(c)) return s;
-  // fields are inputs when given: restore them (a previous run overwrote them)
-  if (c->fields_given) {
-    const size_t fbytes = c->lo.status - c->lo.fields;
-    HIP_TRY(hipMemcpyAsync(c->ws + c->lo.fields, c->host_in.data() + c->lo.fields, fbytes, hipMemcpyHostToDevice,
-                           c->stream));
-  }
-  HIP_TRY(launch_zero(c->ws + c->lo.queues, sizeof(int32_t) * 64, c->stream));
-  if (hfqmc_status s = ensure_events(c, 2 * c->groups.size())) return s;
-  const ImpDesc* descs = reinterpret_cast<const ImpDesc*>(c->ws + c->lo.descs);
-  const int32_t* order = reinterpret_cast<const int32_t*>(c->ws + c->lo.order);
-  int* queues = reinterpret_cast<int*>(c->ws + c->lo.queues);
-  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
-    const Group& gr = c->groups[gi];
-    HIP_TRY(hipEventRecord(c->ev[2 * gi], c->stream));
-    HIP_TRY(launch_sweep(gr.k, gr.grid, c->stream, descs, order + gr.first, gr.count, queues + gi, c->ws));
-    HIP_TRY(hipEventRecord(c->ev[2 * gi + 1], c->stream));
-  }
+  TRY(set_device(c));
+  HIP_TRY(hipEventRecord(c->ev_start, c->stream));
+  TRY(enqueue_pass(c, c->stream, true));
+  HIP_TRY(hipEventRecord(c->ev_end, c->stream));
   c->last_launches = (int)c->groups.size();
+  c->last_timed_groups = true;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_run_graph(hfqmc_ctx* c) {
+  if (!c || !c->staged) return fail(HFQMC_EINVAL, "hfqmc_run_graph: nothing staged");
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  if (!c->gexec) {
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    const hfqmc_status st = enqueue_pass(c, c->cap, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (st != HFQMC_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (st != HFQMC_OK) return st;
+      HIP_TRY(e);
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(ei);
+  }
+  HIP_TRY(hipEventRecord(c->ev_start, c->stream));
+  HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+  HIP_TRY(hipEventRecord(c->ev_end, c->stream));
+  c->last_launches = (int)c->groups.size();
+  c->last_timed_groups = false;
   return HFQMC_OK;
 }
 
@@ -541,29 +1065,41 @@ hfqmc_status hfqmc_last_run_ms(hfqmc_ctx* c, double* ms, int32_t* n_launches) {
   if (!c || !ms) return fail(HFQMC_EINVAL, "hfqmc_last_run_ms: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (c->last_launches == 0) return fail(HFQMC_EINVAL, "no run recorded");
-  HIP_TRY(hipEventSynchronize(c->ev[2 * c->last_launches - 1]));
-  float t = 0.f;
-  HIP_TRY(hipEventElapsedTime(&t, c->ev[0], c->ev[2 * c->last_launches - 1]));
-  *ms = t;
+  TRY(pass_ms(c, ms));
   if (n_launches) *n_launches = c->last_launches;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx* c, int32_t i, double* ms, int32_t* L_padded, int32_t* n_items) {
+  if (!c || !ms) return fail(HFQMC_EINVAL, "hfqmc_last_launch_ms: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->last_launches == 0 || !c->last_timed_groups)
+    return fail(HFQMC_EINVAL, "no eagerly launched run recorded (graph replays time the whole pass only)");
+  if (i < 0 || i >= c->last_launches) return fail(HFQMC_EINVAL, "launch %d outside [0,%d)", i, c->last_launches);
+  HIP_TRY(hipEventSynchronize(c->ev[2 * i + 1]));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]));
+  *ms = t;
+  if (L_padded) *L_padded = c->groups[i].LT;
+  if (n_items) *n_items = c->groups[i].count;
   return HFQMC_OK;
 }
 
 hfqmc_status hfqmc_collect(hfqmc_ctx* c, hfqmc_result* out) {
   if (!c || !c->staged || !out) return fail(HFQMC_EINVAL, "hfqmc_collect: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
-  if (hfqmc_status s = set_device(c)) return s;
+  TRY(set_device(c));
   const size_t lo_off = c->lo.fields, hi_off = c->lo.state;
-  c->host_out.resize(hi_off - lo_off);
-  HIP_TRY(hipMemcpyAsync(c->host_out.data(), c->ws + lo_off, hi_off - lo_off, hipMemcpyDeviceToHost, c->stream));
+  std::vector<uint8_t> host(hi_off - lo_off);
+  HIP_TRY(hipMemcpyAsync(host.data(), c->ws + lo_off, hi_off - lo_off, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   hfqmc_status worst = HFQMC_OK;
   for (size_t i = 0; i < c->probs.size(); ++i) {
     const hfqmc_problem& p = c->probs[i];
-    const double* sums = reinterpret_cast<const double*>(c->host_out.data() + (c->lo.b_off[i] - lo_off));
+    const double* sums = reinterpret_cast<const double*>(host.data() + (c->lo.b_off[i] - lo_off));
     const ImpStatus* st =
-        reinterpret_cast<const ImpStatus*>(c->host_out.data() + (c->lo.status - lo_off) + sizeof(ImpStatus) * i);
-    const int8_t* fields = reinterpret_cast<const int8_t*>(c->host_out.data() + (c->lo.f_off[i] - lo_off));
+        reinterpret_cast<const ImpStatus*>(host.data() + (c->lo.status - lo_off) + sizeof(ImpStatus) * i);
+    const int8_t* fields = reinterpret_cast<const int8_t*>(host.data() + (c->lo.f_off[i] - lo_off));
     finalise(p, sums, *st, fields, out[i]);
     if (out[i].status != HFQMC_OK) worst = (hfqmc_status)out[i].status;
   }
@@ -574,11 +1110,93 @@ hfqmc_status hfqmc_collect(hfqmc_ctx* c, hfqmc_result* out) {
 hfqmc_status hfqmc_solve(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
                          hfqmc_result* out) {
   if (!out) return fail(HFQMC_EINVAL, "hfqmc_solve: out is NULL");
-  hfqmc_status s = hfqmc_stage(c, p, n, d_ws, ws_bytes);
-  if (s) return s;
-  s = hfqmc_run(c);
-  if (s) return s;
+  TRY(hfqmc_stage(c, p, n, d_ws, ws_bytes));
+  TRY(hfqmc_run(c));
   return hfqmc_collect(c, out);
+}
+
+// ---------------------------------------------------------------- tuning
+
+hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
+                        int32_t sweeps) {
+  if (!c || !p || n < 1 || !d_ws || sweeps < 4) return fail(HFQMC_EINVAL, "hfqmc_tune: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  for (int i = 0; i < n; ++i) TRY(validate(p[i], i));
+  std::vector<int> classes;
+  for (int i = 0; i < n; ++i) classes.push_back(padded_L(p[i].L));
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  const int dk_delayed = c->prec == HFQMC_MIXED ? 2 : 1;
+  for (int LT : classes) {
+    // the class's problems with shortened chains (same Weiss, U, beta, seeds)
+    std::vector<hfqmc_problem> sample;
+    int64_t props = 0;
+    for (int i = 0; i < n; ++i)
+      if (padded_L(p[i].L) == LT) {
+        hfqmc_problem q = p[i];
+        q.n_warmup = sweeps / 2;
+        q.n_measure = sweeps - sweeps / 2;
+        q.n_bins = 2;
+        sample.push_back(q);
+        props += (int64_t)sweeps * q.L;
+      }
+    std::vector<Plan> cands;
+    for (int dk : {0, dk_delayed}) {
+      int rts[16];
+      const int nv = std::min(16, kernel_variants(LT, dk, rts, 16));
+      for (int v = 0; v < nv; ++v) {
+        if (dk == 0) {
+          cands.push_back({rts[v], 0, 1});
+        } else {
+          for (int k : {4, 8, 16, 32}) cands.push_back({rts[v], dk, k});
+        }
+      }
+    }
+    TuneEntry best{prec_name(c->prec), LT, 0, 0, -1.0};
+    for (const Plan& pl : cands) {
+      TRY(stage_impl(c, sample.data(), (int)sample.size(), d_ws, ws_bytes, &pl));
+      double ms = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_TRY(hipEventRecord(c->ev_start, c->stream));
+        TRY(enqueue_pass(c, c->stream, false));
+        HIP_TRY(hipEventRecord(c->ev_end, c->stream));
+        double t = 0;
+        TRY(pass_ms(c, &t));
+        if (rep > 0) ms = std::min(ms, t);
+      }
+      const double rate = (double)props / (ms * 1e-3);
+      if (rate > best.rate) best = {prec_name(c->prec), LT, pl.rt, pl.k, rate};
+    }
+    c->tune[LT] = best;
+    bool replaced = false;
+    for (auto& t : c->tune_all)
+      if (t.prec == best.prec && t.LT == LT) {
+        t = best;
+        replaced = true;
+      }
+    if (!replaced) c->tune_all.push_back(best);
+  }
+  c->staged = false;  // the workspace now holds the last tuning run
+  c->last_launches = 0;
+  if (!c->tune_path.empty() && !write_tune_cache(c->tune_path, c->tune_all))
+    return fail(HFQMC_EINVAL, "cannot write tune cache %s", c->tune_path.c_str());
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_plan(hfqmc_ctx* c, int32_t L, int32_t delay, int32_t* rt, int32_t* k, double* tuned_rate) {
+  if (!c || L < 1 || L > kMaxL || delay < 0 || delay > kMaxDelay) return fail(HFQMC_EINVAL, "hfqmc_plan: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  hfqmc_problem p{};
+  p.L = L;
+  p.delay = delay;
+  const Plan pl = plan_for(c, p);
+  if (rt) *rt = pl.rt;
+  if (k) *k = pl.k;
+  if (tuned_rate) {
+    auto it = c->tune.find(padded_L(L));
+    *tuned_rate = it == c->tune.end() ? 0.0 : it->second.rate;
+  }
+  return HFQMC_OK;
 }
 
 // ---------------------------------------------------------------- sites
@@ -586,7 +1204,7 @@ hfqmc_status hfqmc_solve(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* 
 hfqmc_status hfqmc_attach_pool(hfqmc_ctx* c, void* d_pool, size_t bytes) {
   if (!c || !d_pool || bytes < 4096) return fail(HFQMC_EINVAL, "hfqmc_attach_pool: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
-  if (!c->sites.empty()) return fail(HFQMC_EINVAL, "hfqmc_attach_pool: sites still open");
+  if (!c->sites.empty() || c->srv.started) return fail(HFQMC_EINVAL, "hfqmc_attach_pool: pool in use");
   c->pool = reinterpret_cast<uint8_t*>(d_pool);
   c->pool_bytes = bytes;
   c->free_list.assign(1, PoolBlock{0, bytes / 256 * 256});
@@ -611,7 +1229,10 @@ hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, hfqmc_site
   if (!s) return fail(HFQMC_ENOMEM, "out of host memory");
   s->L = L;
   s->LT = padded_L(L);
-  s->RT = choose_rt(s->LT);
+  hfqmc_problem p{};
+  p.L = L;
+  p.delay = 1;
+  s->RT = plan_for(c, p).rt;
   s->n_bins = n_bins;
   s->bytes = site_layout(s);
   if (hfqmc_status st = pool_alloc(c, s->bytes, &s->off)) {
@@ -628,28 +1249,20 @@ hfqmc_status hfqmc_site_close(hfqmc_ctx* c, hfqmc_site* s) {
   std::lock_guard<std::mutex> g(c->mu);
   auto it = std::find(c->sites.begin(), c->sites.end(), s);
   if (it == c->sites.end()) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   pool_free(c, s->off, s->bytes);
   c->sites.erase(it);
   delete s;
   return HFQMC_OK;
 }
 
-static bool site_known(hfqmc_ctx* c, hfqmc_site* s) {
-  return std::find(c->sites.begin(), c->sites.end(), s) != c->sites.end();
-}
-
-hfqmc_status hfqmc_site_define(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p) {
-  if (!c || !s || !p) return fail(HFQMC_EINVAL, "hfqmc_site_define: bad arguments");
-  std::lock_guard<std::mutex> g(c->mu);
-  if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
-  if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
-  if (hfqmc_status st = validate(*p, 0)) return st;
-  if (hfqmc_status st = set_device(c)) return st;
+static hfqmc_status site_upload_problem(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p, hipStream_t st) {
   uint8_t* base = c->pool + s->off;
-  HIP_TRY(hipMemcpyAsync(base + s->o_weiss, p->weiss[0], sizeof(double) * s->L, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(base + s->o_weiss, p->weiss[0], sizeof(double) * s->L, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(base + s->o_weiss + sizeof(double) * s->L, p->weiss[1], sizeof(double) * s->L,
-                         hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+                         hipMemcpyHostToDevice, st));
+  if (p->init_fields) HIP_TRY(hipMemcpyAsync(base + s->o_init, p->init_fields, s->L, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
   s->prob = *p;
   s->prob.weiss[0] = s->prob.weiss[1] = nullptr;
   s->prob.init_fields = nullptr;
@@ -657,21 +1270,33 @@ hfqmc_status hfqmc_site_define(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem*
   return HFQMC_OK;
 }
 
+hfqmc_status hfqmc_site_define(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p) {
+  if (!c || !s || !p) return fail(HFQMC_EINVAL, "hfqmc_site_define: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
+  if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
+  TRY(validate(*p, 0));
+  TRY(set_device(c));
+  return site_upload_problem(c, s, p, c->stream);
+}
+
 hfqmc_status hfqmc_site_set_fields(hfqmc_ctx* c, hfqmc_site* s, const int8_t* fields) {
   if (!c || !s || !fields) return fail(HFQMC_EINVAL, "hfqmc_site_set_fields: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   if (!s->defined) return fail(HFQMC_EINVAL, "site has no problem (call hfqmc_site_define)");
   for (int k = 0; k < s->L; ++k)
     if (fields[k] != 1 && fields[k] != -1) return fail(HFQMC_EINVAL, "fields[%d] not +-1", k);
-  if (hfqmc_status st = set_device(c)) return st;
-  HIP_TRY(hipMemcpyAsync(c->pool + s->off + s->o_fields, fields, s->L, hipMemcpyHostToDevice, c->stream));
+  TRY(set_device(c));
+  HIP_TRY(hipMemcpyAsync(c->pool + s->off + s->o_init, fields, s->L, hipMemcpyHostToDevice, c->stream));
   ImpDesc d{};
   fill_constants(d, s->prob);
   d.op = OP_FORCE;
   d.n_force = 0;
   d.flags = F_FIELDS_GIVEN | F_SAVE | F_ZERO_ACC;
-  if (hfqmc_status st = site_launch(c, s, d)) return st;
+  TRY(site_launch(c, s, d));
   s->has_state = true;
   return HFQMC_OK;
 }
@@ -680,10 +1305,11 @@ hfqmc_status hfqmc_site_force_flips(hfqmc_ctx* c, hfqmc_site* s, const int32_t* 
   if (!c || !s || n < 0 || (n > 0 && !slices)) return fail(HFQMC_EINVAL, "hfqmc_site_force_flips: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   if (!s->has_state) return fail(HFQMC_EINVAL, "site has no state (call hfqmc_site_set_fields)");
   for (int k = 0; k < n; ++k)
     if (slices[k] < 0 || slices[k] >= s->L) return fail(HFQMC_EINVAL, "slice %d outside [0,%d)", slices[k], s->L);
-  if (hfqmc_status st = set_device(c)) return st;
+  TRY(set_device(c));
   uint8_t* base = c->pool + s->off;
   for (int k0 = 0; k0 < n; k0 += 1024) {
     const int m = std::min(1024, n - k0);
@@ -693,7 +1319,7 @@ hfqmc_status hfqmc_site_force_flips(hfqmc_ctx* c, hfqmc_site* s, const int32_t* 
     d.op = OP_FORCE;
     d.n_force = m;
     d.flags = F_RESUME | F_SAVE;
-    if (hfqmc_status st = site_launch(c, s, d)) return st;
+    TRY(site_launch(c, s, d));
     if (ratios) {
       HIP_TRY(hipMemcpy(ratios + k0, base + s->o_force + 4 * ((m + 1) & ~1), sizeof(double) * m,
                         hipMemcpyDeviceToHost));
@@ -706,13 +1332,14 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx* c, hfqmc_site* s, double* drift) {
   if (!c || !s) return fail(HFQMC_EINVAL, "hfqmc_site_recompute: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   if (!s->has_state) return fail(HFQMC_EINVAL, "site has no state");
-  if (hfqmc_status st = set_device(c)) return st;
+  TRY(set_device(c));
   ImpDesc d{};
   fill_constants(d, s->prob);
   d.op = OP_RECOMPUTE;
   d.flags = F_RESUME | F_SAVE | F_ZERO_ACC;
-  if (hfqmc_status st = site_launch(c, s, d)) return st;
+  TRY(site_launch(c, s, d));
   if (drift) {
     ImpStatus st;
     HIP_TRY(hipMemcpy(&st, c->pool + s->off + s->o_status, sizeof st, hipMemcpyDeviceToHost));
@@ -725,8 +1352,9 @@ hfqmc_status hfqmc_site_get_green(hfqmc_ctx* c, hfqmc_site* s, int32_t spin, dou
   if (!c || !s || !out || (spin != 0 && spin != 1)) return fail(HFQMC_EINVAL, "hfqmc_site_get_green: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   if (!s->has_state) return fail(HFQMC_EINVAL, "site has no state");
-  if (hfqmc_status st = set_device(c)) return st;
+  TRY(set_device(c));
   std::vector<double> st((size_t)2 * s->LT * s->LT);
   HIP_TRY(hipMemcpyAsync(st.data(), c->pool + s->off + s->o_state, sizeof(double) * st.size(), hipMemcpyDeviceToHost,
                          c->stream));
@@ -739,10 +1367,145 @@ hfqmc_status hfqmc_site_get_fields(hfqmc_ctx* c, hfqmc_site* s, int8_t* fields) 
   if (!c || !s || !fields) return fail(HFQMC_EINVAL, "hfqmc_site_get_fields: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
   if (!s->has_state) return fail(HFQMC_EINVAL, "site has no state");
-  if (hfqmc_status st = set_device(c)) return st;
+  TRY(set_device(c));
   HIP_TRY(hipMemcpyAsync(fields, c->pool + s->off + s->o_fields, s->L, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return HFQMC_OK;
+}
+
+// ---------------------------------------------------------------- serving
+
+hfqmc_status hfqmc_serve_config(hfqmc_ctx* c, int64_t quantum_proposals, double capacity_cus) {
+  if (!c || quantum_proposals < 1 || capacity_cus < 0) return fail(HFQMC_EINVAL, "hfqmc_serve_config: bad arguments");
+  std::lock_guard<std::mutex> g(c->srv.mu);
+  c->srv.quantum = quantum_proposals;
+  c->srv.capacity = capacity_cus > 0 ? capacity_cus : (double)c->n_cu;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_submit(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p, uint64_t* ticket) {
+  if (!c || !s || !p || !ticket) return fail(HFQMC_EINVAL, "hfqmc_submit: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
+  if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
+  if (p->delay > 1) return fail(HFQMC_EINVAL, "serving runs rank-one updates (delay 0 or 1)");
+  TRY(validate(*p, 0));
+  TRY(srv_start(c));
+  Server& S = c->srv;
+  {
+    std::lock_guard<std::mutex> gs(S.mu);
+    if (S.failed) return fail(HFQMC_EDEVICE, "serving engine failed: %s", S.error.c_str());
+    if (s->busy) return fail(HFQMC_EAGAIN, "site has a request in progress");
+    if (S.pending.size() >= S.max_pending) return fail(HFQMC_EAGAIN, "request queue full");
+    s->busy = true;  // no launch touches the site until the request is queued
+  }
+  const bool had_state = s->has_state;
+  if (hfqmc_status st = site_upload_problem(c, s, p, S.io)) {
+    std::lock_guard<std::mutex> gs(S.mu);
+    s->busy = false;
+    return st;
+  }
+  Request* r = new (std::nothrow) Request;
+  if (!r) {
+    std::lock_guard<std::mutex> gs(S.mu);
+    s->busy = false;
+    return fail(HFQMC_ENOMEM, "out of host memory");
+  }
+  r->site = s;
+  r->prob = s->prob;
+  r->total = p->n_warmup + p->n_measure;
+  r->given = p->init_fields != nullptr;
+  r->keep = !r->given && had_state;
+  r->weight = 1.0 / site_bpc(s);
+  {
+    std::lock_guard<std::mutex> gs(S.mu);
+    r->ticket = S.next_ticket++;
+    S.tickets[r->ticket] = r;
+    S.pending.push_back(r);
+    ++S.submitted;
+    *ticket = r->ticket;
+  }
+  S.cv.notify_all();
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_poll(hfqmc_ctx* c, uint64_t ticket, hfqmc_result* out) {
+  if (!c || !out) return fail(HFQMC_EINVAL, "hfqmc_poll: bad arguments");
+  Server& S = c->srv;
+  std::lock_guard<std::mutex> gs(S.mu);
+  auto it = S.tickets.find(ticket);
+  if (it == S.tickets.end() || it->second->cancel) return fail(HFQMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  if (r->state != R_DONE) return HFQMC_EAGAIN;
+  const int L = r->site->L;
+  for (int k = 0; k < 2; ++k) {
+    if (out->g[k] && !r->g[k].empty()) std::memcpy(out->g[k], r->g[k].data(), sizeof(double) * (L + 1));
+    if (out->g_err[k] && !r->gerr[k].empty()) std::memcpy(out->g_err[k], r->gerr[k].data(), sizeof(double) * (L + 1));
+  }
+  if (out->bins && !r->bins.empty()) std::memcpy(out->bins, r->bins.data(), sizeof(double) * r->bins.size());
+  if (out->final_fields && !r->fields.empty()) std::memcpy(out->final_fields, r->fields.data(), L);
+  for (int k = 0; k < 2; ++k) {
+    out->n[k] = r->res.n[k];
+    out->n_err[k] = r->res.n_err[k];
+  }
+  out->docc = r->res.docc;
+  out->docc_err = r->res.docc_err;
+  out->accept_rate = r->res.accept_rate;
+  out->max_drift = r->res.max_drift;
+  out->proposals = r->res.proposals;
+  out->accepts = r->res.accepts;
+  out->nonpositive = r->res.nonpositive;
+  out->status = r->status;
+  const hfqmc_status st = r->status;
+  S.tickets.erase(it);
+  delete r;
+  if (st != HFQMC_OK) return fail(st, "request %llu failed%s%s", (unsigned long long)ticket, S.error.empty() ? "" : ": ",
+                                  S.error.c_str());
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_cancel(hfqmc_ctx* c, uint64_t ticket) {
+  if (!c) return fail(HFQMC_EINVAL, "hfqmc_cancel: bad arguments");
+  Server& S = c->srv;
+  std::lock_guard<std::mutex> gs(S.mu);
+  auto it = S.tickets.find(ticket);
+  if (it == S.tickets.end() || it->second->cancel) return fail(HFQMC_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  if (r->state == R_PENDING || r->state == R_READY || r->state == R_DONE) {
+    if (r->state == R_PENDING) S.pending.erase(std::find(S.pending.begin(), S.pending.end(), r));
+    if (r->state == R_READY) {
+      S.ready.erase(std::find(S.ready.begin(), S.ready.end(), r));
+      S.used -= r->weight;
+    }
+    if (r->state != R_DONE) {
+      r->site->busy = false;
+      if (!r->first) r->site->has_state = true;
+      ++S.cancelled;
+    }
+    S.tickets.erase(it);
+    delete r;
+  } else {
+    r->cancel = true;  // in flight: dropped when its launch retires
+  }
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_serve_stats(hfqmc_ctx* c, hfqmc_serve_stats_t* out) {
+  if (!c || !out) return fail(HFQMC_EINVAL, "hfqmc_serve_stats: bad arguments");
+  Server& S = c->srv;
+  std::lock_guard<std::mutex> gs(S.mu);
+  out->submitted = S.submitted;
+  out->completed = S.completed;
+  out->cancelled = S.cancelled;
+  out->launches = S.launches;
+  out->pending = (int32_t)S.pending.size();
+  int32_t inflight = 0;
+  for (const auto& L : S.inflight) inflight += (int32_t)L.items.size();
+  out->active = (int32_t)S.ready.size() + inflight;
+  out->capacity_used = S.used;
+  out->capacity = S.capacity > 0 ? S.capacity : (double)c->n_cu;
   return HFQMC_OK;
 }
 

@@ -19,10 +19,11 @@ enum Op : int32_t {
 
 // Item flags.
 enum Flags : int32_t {
-  F_FIELDS_GIVEN = 1,  // take the initial fields from the fields array, else draw them
+  F_FIELDS_GIVEN = 1,  // take the initial fields from the init array, else draw them
   F_RESUME = 2,        // load fields and G tiles from the state area (no fresh Dyson)
   F_SAVE = 4,          // store fields and G tiles to the state area at the end
   F_ZERO_ACC = 8,      // clear bins and status before running
+  F_KEEP_FIELDS = 16,  // take the fields left in the fields array, fresh Dyson
 };
 
 // One impurity work item.  All offsets are in bytes from the workspace base.
@@ -53,6 +54,8 @@ struct alignas(16) ImpDesc {
   int64_t off_status;       // ImpStatus
   int64_t off_state;        // 2 x LT x LT doubles: G tiles in lane order
   int64_t off_force;        // OP_FORCE: n_force int32 slices, then n_force doubles ratios
+  int64_t off_init;         // F_FIELDS_GIVEN: L int8 initial fields (read only)
+  int64_t pad_;
 };
 
 struct alignas(16) ImpStatus {

@@ -591,10 +591,11 @@ struct Engine {
       sm.weiss[s][k] = k < L ? wv[s * L + k] : 0.0;
     }
     // fields
-    if (flags & (F_FIELDS_GIVEN | F_RESUME)) {
+    if (flags & (F_FIELDS_GIVEN | F_RESUME | F_KEEP_FIELDS)) {
+      const int8_t* fin = (flags & F_FIELDS_GIVEN) ? reinterpret_cast<const int8_t*>(ws + d.off_init) : fields;
       static_for<JW>([&](auto jj) __attribute__((always_inline)) {
         const int m = lane + 64 * jj;
-        set_field(jj, m < L ? (fields[m] < 0 ? -1 : 1) : 1);
+        set_field(jj, m < L ? (fin[m] < 0 ? -1 : 1) : 1);
       });
     } else {
       const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d.seed, d.site);
@@ -613,8 +614,12 @@ struct Engine {
     double max_drift = 0.0;
 
     if (d.op == OP_SWEEPS) {
+      // Running bin sums.  They are loaded when a bin is entered and stored
+      // (not added) when it is left or the launch ends, so a chain split
+      // over several launches sums in exactly the order of one launch.
       double gacc = 0.0;  // thread t < 2L: running bin sum of g_s(tau_k), s = t / L, k = t % L
       double nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
+      int64_t cur_bin = -1;
       const int64_t nm = d.n_measure, nb = d.n_bins;
       int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
@@ -663,6 +668,14 @@ struct Engine {
         if (w >= d.n_warmup) {
           const int64_t m = w - d.n_warmup;
           const int64_t b = (m * nb) / nm;
+          double* bp = bins + (size_t)b * NV;
+          if (b != cur_bin) {
+            gacc = tid < 2 * L ? bp[tid + (tid >= L)] : 0.0;
+            nacc_u = bp[2 * L + 2];
+            nacc_d = bp[2 * L + 3];
+            dacc = bp[2 * L + 4];
+            cur_bin = b;
+          }
           // density and double occupancy from the diagonals
           double xu = 0.0, xd = 0.0, xx = 0.0;
           static_for<JW>([&](auto jj) __attribute__((always_inline)) {
@@ -679,17 +692,15 @@ struct Engine {
           measure_green(gacc);
           const bool last = (m + 1 == nm) || (((m + 1) * nb) / nm != b) || (w + 1 == d.sweep_end);
           if (last) {
-            double* bp = bins + (size_t)b * NV;
-            if (tid < 2 * L) bp[tid + (tid >= L)] += gacc;
+            if (tid < 2 * L) bp[tid + (tid >= L)] = gacc;
             if (tid == 0) {
-              bp[L] += nacc_u;
-              bp[2 * L + 1] += nacc_d;
-              bp[2 * L + 2] += nacc_u;
-              bp[2 * L + 3] += nacc_d;
-              bp[2 * L + 4] += dacc;
+              bp[L] = nacc_u;
+              bp[2 * L + 1] = nacc_d;
+              bp[2 * L + 2] = nacc_u;
+              bp[2 * L + 3] = nacc_d;
+              bp[2 * L + 4] = dacc;
             }
-            gacc = 0.0;
-            nacc_u = nacc_d = dacc = 0.0;
+            cur_bin = -1;
           }
         }
       }
@@ -774,6 +785,17 @@ const KernelInfo* find_kernel(int LT, int RT, int DK) {
   for (const auto& k : kKernels)
     if (k.LT == LT && k.RT == RT && k.DK == DK) return &k;
   return nullptr;
+}
+
+// Tile-rows-per-wave variants compiled for (LT, DK); returns their count.
+int kernel_variants(int LT, int DK, int* rt_out, int max) {
+  int n = 0;
+  for (const auto& k : kKernels)
+    if (k.LT == LT && k.DK == DK) {
+      if (n < max) rt_out[n] = k.RT;
+      ++n;
+    }
+  return n;
 }
 
 int kernel_threads(const KernelInfo* k) { return k->threads; }

@@ -48,6 +48,13 @@ class Result(C.Structure):
     ]
 
 
+class ServeStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64), ("launches", C.c_int64),
+        ("pending", C.c_int32), ("active", C.c_int32), ("capacity_used", C.c_double), ("capacity", C.c_double),
+    ]
+
+
 _lib = None
 _VP = C.c_void_p
 
@@ -79,6 +86,17 @@ def lib():
             "hfqmc_site_get_green": [_VP, _VP, C.c_int32, C.POINTER(C.c_double)],
             "hfqmc_site_get_fields": [_VP, _VP, C.POINTER(C.c_int8)],
             "hfqmc_site_recompute": [_VP, _VP, C.POINTER(C.c_double)],
+            "hfqmc_run_graph": [_VP],
+            "hfqmc_last_launch_ms": [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)],
+            "hfqmc_tune": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t, C.c_int32],
+            "hfqmc_plan": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_double)],
+            "hfqmc_serve_config": [_VP, C.c_int64, C.c_double],
+            "hfqmc_submit": [_VP, _VP, C.POINTER(Problem), C.POINTER(C.c_uint64)],
+            "hfqmc_poll": [_VP, C.c_uint64, C.POINTER(Result)],
+            "hfqmc_cancel": [_VP, C.c_uint64],
+            "hfqmc_serve_stats": [_VP, C.POINTER(ServeStats)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -180,17 +198,19 @@ def _torch():
 class Context:
     """A library context bound to a device and a HIP stream (torch's current one by default)."""
 
-    def __init__(self, device: int = 0, stream=None, precision: int = FP64):
+    def __init__(self, device: int = 0, stream=None, precision: int = FP64, tune_cache: str | None = None):
         torch = _torch()
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
         h = _VP()
-        _check(lib().hfqmc_create(device, _VP(stream.cuda_stream), precision, None, C.byref(h)), "hfqmc_create")
+        tc = None if tune_cache is None else os.fsencode(tune_cache)
+        _check(lib().hfqmc_create(device, _VP(stream.cuda_stream), precision, tc, C.byref(h)), "hfqmc_create")
         self.h = h
         self._staged = None
         self._pool = None
+        self._tickets = {}
 
     def close(self):
         if self.h:
@@ -239,11 +259,73 @@ class Context:
             _check(st, "hfqmc_collect")
         return res
 
+    def run_graph(self):
+        _check(lib().hfqmc_run_graph(self.h), "hfqmc_run_graph")
+
     def last_run_ms(self):
         ms = C.c_double()
         n = C.c_int32()
         _check(lib().hfqmc_last_run_ms(self.h, C.byref(ms), C.byref(n)), "hfqmc_last_run_ms")
         return ms.value, n.value
+
+    def last_launch_ms(self, i: int = 0):
+        """(ms, padded L, items) of class kernel i of the last eager run."""
+        ms, lt, n = C.c_double(), C.c_int32(), C.c_int32()
+        _check(lib().hfqmc_last_launch_ms(self.h, i, C.byref(ms), C.byref(lt), C.byref(n)), "hfqmc_last_launch_ms")
+        return ms.value, lt.value, n.value
+
+    # ---------------------------------------------------------------- tuning
+    def tune(self, problems, sweeps: int = 64, workspace=None):
+        if workspace is None:
+            workspace = self.alloc_workspace(problems)
+        P = _Problems(problems)
+        _check(lib().hfqmc_tune(self.h, P.arr, P.n, _VP(workspace.data_ptr()),
+                                workspace.numel() * workspace.element_size(), int(sweeps)), "hfqmc_tune")
+        self._staged = None
+
+    def plan(self, L: int, delay: int = 0):
+        """(tile-rows per wave, delay depth, tuned proposals/s or 0)."""
+        rt, k, rate = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().hfqmc_plan(self.h, L, delay, C.byref(rt), C.byref(k), C.byref(rate)), "hfqmc_plan")
+        return rt.value, k.value, rate.value
+
+    # ---------------------------------------------------------------- serving
+    def serve_config(self, quantum_proposals: int = 16384, capacity_cus: float = 0.0):
+        _check(lib().hfqmc_serve_config(self.h, int(quantum_proposals), float(capacity_cus)), "hfqmc_serve_config")
+
+    def submit(self, site: "Site", problem) -> int | None:
+        """Queue a request; returns its ticket, or None if not admissible now (EAGAIN)."""
+        P = _Problems([problem])
+        t = C.c_uint64()
+        st = lib().hfqmc_submit(self.h, site.h, P.arr, C.byref(t))
+        if st == EAGAIN:
+            return None
+        _check(st, "hfqmc_submit")
+        self._tickets[t.value] = dict(problem)
+        return t.value
+
+    def poll(self, ticket: int):
+        """Result dict once the request is done, else None."""
+        prob = self._tickets.get(ticket)
+        if prob is None:
+            raise HFQMCError(ENOTFOUND, f"hfqmc_poll: unknown ticket {ticket}")
+        R = _Results([prob])
+        st = lib().hfqmc_poll(self.h, ticket, R.arr)
+        if st == EAGAIN:
+            return None
+        del self._tickets[ticket]
+        if st not in (OK, ENUMERIC):
+            _check(st, "hfqmc_poll")
+        return R.to_list()[0]
+
+    def cancel(self, ticket: int):
+        _check(lib().hfqmc_cancel(self.h, ticket), "hfqmc_cancel")
+        self._tickets.pop(ticket, None)
+
+    def serve_stats(self) -> dict:
+        s = ServeStats()
+        _check(lib().hfqmc_serve_stats(self.h, C.byref(s)), "hfqmc_serve_stats")
+        return {k: getattr(s, k) for k, _ in ServeStats._fields_}
 
     # ---------------------------------------------------------------- sites
     def attach_pool(self, nbytes: int):

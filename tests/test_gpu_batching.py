@@ -1,0 +1,135 @@
+"""Batch scheduling on the GPU, through the C ABI: concurrent kernel classes,
+graph replay, given initial fields without host copies, and the autotuner.
+
+Every check is exact: results depend only on each problem (Philox keyed by
+seed and site), so a scheduling change may not change a single bit, and the
+rank-one path under any tile shape reproduces the oracle's trajectory.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1006_2716_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1006_2716_amd import hfqmc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = hfqmc.Context(0)
+    yield c
+    c.close()
+
+
+def _uneven(n=40, Ls=(17, 32, 40, 64, 80, 96, 128), sweeps=(6, 30), seed=9):
+    probs = wl.chain_batch(n_imp=n, Ls=Ls, n_warmup=sweeps[0], n_measure=sweeps[1], seed=seed)
+    for p in probs:
+        p["n_bins"] = 4
+        p["recompute_every"] = 7
+    return probs
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for k in ("g_up", "g_dn", "bins", "fields"):
+            assert np.array_equal(x[k], y[k]), k
+        for k in ("proposals", "accepts", "nonpositive", "max_drift", "n_up", "n_dn", "docc"):
+            assert x[k] == y[k], k
+
+
+def test_concurrent_classes_time_each_launch(ctx):
+    probs = _uneven()
+    print(f"uneven batch of {len(probs)}", flush=True)
+    ctx.stage(probs)
+    ctx.run()
+    res = ctx.collect()
+    ms, n = ctx.last_run_ms()
+    assert n == len({(p["L"] + 15) // 16 for p in probs})
+    seen = 0
+    for i in range(n):
+        t, lt, items = ctx.last_launch_ms(i)
+        assert 0 < t <= ms * 1.001 and lt % 16 == 0
+        seen += items
+    assert seen == len(probs)
+    assert all(r["status"] == 0 for r in res)
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(ctx):
+    probs = _uneven(seed=10)
+    print("graph replay", flush=True)
+    ctx.stage(probs)
+    ctx.run()
+    ref = ctx.collect()
+    for rep in range(3):
+        ctx.run_graph()
+        got = ctx.collect()
+        _same(got, ref)
+        ctx.run()  # eager work between replays
+        _same(ctx.collect(), ref)
+    ctx.run_graph()
+    ms, _ = ctx.last_run_ms()
+    assert ms > 0
+    _same(ctx.collect(), ref)
+
+
+def test_given_fields_survive_repeated_runs(ctx):
+    probs = _uneven(n=12, seed=11)
+    rng = np.random.default_rng(5)
+    for p in probs:
+        p["init_fields"] = rng.choice([-1, 1], p["L"]).astype(np.int8)
+    ctx.stage(probs)
+    ctx.run()
+    a = ctx.collect()
+    ctx.run()
+    ctx.run_graph()
+    b = ctx.collect()
+    _same(a, b)
+    ref = oracle.run(probs[:4], n_threads=4)
+    for p, g, r in zip(probs[:4], a[:4], ref):
+        assert np.array_equal(g["fields"], r["fields"]), p["L"]
+        assert g["proposals"] == r["proposals"] and g["accepts"] == r["accepts"]
+
+
+def test_autotuner_picks_measured_shape_and_persists(tmp_path):
+    import torch
+    from paper_1006_2716_amd import hfqmc
+    probs = wl.chain_batch(n_imp=96, Ls=(32, 48, 64), n_warmup=4, n_measure=12, seed=12)
+    for p in probs:
+        p["n_bins"] = 4
+    cache = tmp_path / "tune.json"
+    c = hfqmc.Context(0, tune_cache=str(cache))
+    try:
+        print("tuning", flush=True)
+        c.tune(probs, sweeps=16)
+        data = json.loads(cache.read_text())
+        assert data["arch"] == "gfx950"
+        ents = {e["L_padded"]: e for e in data["entries"] if e["precision"] == "fp64"}
+        assert set(ents) == {32, 48, 64}
+        for LT, e in ents.items():
+            assert e["k"] in (1, 4, 8, 16, 32) and e["proposals_per_s"] > 0
+            rt, k, rate = c.plan(LT, 0)
+            assert (rt, k) == (e["rt"], e["k"]) and rate > 0
+        # a new context reads the same plan from the cache
+        c2 = hfqmc.Context(0, tune_cache=str(cache))
+        for LT, e in ents.items():
+            assert c2.plan(LT, 0)[:2] == (e["rt"], e["k"])
+        # the tuned plan reproduces the oracle's trajectories (fp64 delayed
+        # updates change only rounding)
+        sub = [probs[i] for i in (0, 40, 80)]
+        for p in sub:
+            p["n_warmup"], p["n_measure"] = 5, 20
+        got = c2.solve(sub)
+        ref = oracle.run(sub, n_threads=3)
+        for p, g, r in zip(sub, got, ref):
+            assert np.array_equal(g["fields"], r["fields"]), p["L"]
+            assert g["accepts"] == r["accepts"]
+            assert np.max(np.abs(g["bins"] - r["bins"])) < 1e-8
+        c2.close()
+    finally:
+        c.close()
+        torch.cuda.synchronize()
