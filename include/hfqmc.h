@@ -73,7 +73,7 @@ typedef enum { HFQMC_FP64 = 0, HFQMC_MIXED = 1 } hfqmc_precision;
 typedef struct hfqmc_ctx hfqmc_ctx;   /* opaque; one per device and stream */
 typedef struct hfqmc_site hfqmc_site; /* opaque device-resident impurity state */
 
-/* One impurity problem.  1 <= L <= 128, beta > 0, U >= 0, n_bins >= 2,
+/* One impurity problem.  1 <= L <= 160, beta > 0, U >= 0, n_bins >= 2,
  * n_measure >= n_bins, recompute_every >= 1, Weiss samples finite with
  * g(0+) in (0, 1). */
 typedef struct {
@@ -93,7 +93,10 @@ typedef struct {
                                    1: rank-one Sherman-Morrison updates;
                                    2..32: delayed rank-k updates, flushed into G
                                    every k accepted flips (fp32 products when
-                                   the context precision is HFQMC_MIXED) */
+                                   the context precision is HFQMC_MIXED).
+                                   L > 128 always runs delayed fp64 updates with
+                                   G in device memory: delay 0 means 16, 1..16
+                                   the depth, more is EINVAL */
 } hfqmc_problem;
 
 /* Result of one impurity.  Pointer members are caller-owned and may be NULL. */
@@ -213,8 +216,9 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drif
  * without init_fields on a site that already ran starts from the site's last
  * fields with a fresh Dyson solve (the next DMFT iteration), otherwise from
  * init_fields or drawn fields.  A request's result is bitwise the result of
- * hfqmc_solve on the same problem, whatever else runs beside it.  Serving
- * uses rank-one updates (delay 0 or 1).  The site must not be used by the
+ * hfqmc_solve on the same problem with delay 0, whatever else runs beside
+ * it: a site runs the kernel shape its L had (tuned or default) when it was
+ * opened, whatever the request's delay field.  The site must not be used by the
  * test hooks while it has a request (EAGAIN). */
 
 /* quantum_proposals >= 1 (default 16384); capacity_cus > 0 sets the

@@ -86,12 +86,19 @@ struct Plan {
   int rt = 1, dk = 0, k = 1;
 };
 
-// Untuned default tile-rows per wave (measured best on the L = 64 batch; 1
-// wherever only that variant exists).
+// Untuned default tile-rows per wave: the measured best of the rank-one
+// kernels on full batches (L = 64: 512 impurities; L = 96, 128: about 100),
+// 1 wherever only that variant exists.
 int default_rt(int LT, int dk) {
-  if (LT == 64) return 2;
-  (void)dk;
+  if (dk == 0 && (LT == 64 || LT == 96 || LT == 128)) return 2;
+  if (dk != 0 && LT == 64) return 2;
   return 1;
+}
+
+// Bytes of G state per impurity: both spins plus the drift snapshot.
+size_t state_bytes(int L) {
+  const size_t LT = (size_t)((L + 15) / 16 * 16);
+  return sizeof(double) * 4 * LT * LT;
 }
 
 // HS coupling from cosh(lambda) = exp(dtau U / 2), written as
@@ -192,6 +199,11 @@ void finalise(const hfqmc_problem& p, const double* sums, const ImpStatus& st, c
 // row (wr*RT + rt)*16 + 4*(lane/16) + r, column tj*16 + lane%16, where wave
 // = spin*WPS + wr.
 void tiles_to_rowmajor(const double* st, int L, int LT, int RT, int spin, double* out) {
+  if (RT == 0) {  // global-memory kernel: row-major already
+    for (int i = 0; i < L; ++i)
+      for (int j = 0; j < L; ++j) out[(size_t)i * L + j] = st[(size_t)spin * LT * LT + (size_t)i * LT + j];
+    return;
+  }
   const int NT = LT / 16, WPS = NT / RT;
   const size_t per_lane = (size_t)RT * NT * 4;
   for (int wr = 0; wr < WPS; ++wr)
@@ -261,8 +273,7 @@ Layout plan_layout(const hfqmc_problem* p, int n) {
   lo.s_off.resize(n);
   for (int i = 0; i < n; ++i) {
     lo.s_off[i] = off;
-    const size_t LT = padded_L(p[i].L);
-    off += sizeof(double) * 2 * LT * LT;
+    off += state_bytes(p[i].L);
   }
   lo.total = align_up(off, 256);
   return lo;
@@ -277,6 +288,7 @@ struct TuneEntry {
   std::string prec;
   int LT, rt, k;
   double rate;
+  std::string measured;  // every candidate timed: [rt, k, proposals/s], ...
 };
 
 const char* prec_name(hfqmc_precision p) { return p == HFQMC_MIXED ? "mixed" : "fp64"; }
@@ -308,6 +320,24 @@ bool json_find_str(const std::string& obj, const char* key, std::string* v) {
   return true;
 }
 
+// Text inside the brackets of array `key` (nested brackets kept).
+bool json_find_array(const std::string& obj, const char* key, std::string* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t pos = obj.find(k);
+  if (pos == std::string::npos) return false;
+  const size_t b = obj.find('[', pos + k.size());
+  if (b == std::string::npos) return false;
+  int depth = 0;
+  for (size_t i = b; i < obj.size(); ++i) {
+    if (obj[i] == '[') ++depth;
+    if (obj[i] == ']' && --depth == 0) {
+      *v = obj.substr(b + 1, i - b - 1);
+      return true;
+    }
+  }
+  return false;
+}
+
 std::vector<TuneEntry> read_tune_cache(const std::string& path) {
   std::vector<TuneEntry> out;
   std::ifstream f(path);
@@ -329,6 +359,7 @@ std::vector<TuneEntry> read_tune_cache(const std::string& path) {
     if (json_find_str(obj, "precision", &t.prec) && json_find_num(obj, "L_padded", &LT) &&
         json_find_num(obj, "rt", &rt) && json_find_num(obj, "k", &k)) {
       json_find_num(obj, "proposals_per_s", &rate);
+      json_find_array(obj, "measured", &t.measured);
       t.LT = (int)LT;
       t.rt = (int)rt;
       t.k = (int)k;
@@ -346,8 +377,11 @@ bool write_tune_cache(const std::string& path, const std::vector<TuneEntry>& v) 
   if (!f) return false;
   std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
   for (size_t i = 0; i < v.size(); ++i)
-    std::fprintf(f, "  {\"precision\": \"%s\", \"L_padded\": %d, \"rt\": %d, \"k\": %d, \"proposals_per_s\": %.6g}%s\n",
-                 v[i].prec.c_str(), v[i].LT, v[i].rt, v[i].k, v[i].rate, i + 1 < v.size() ? "," : "");
+    std::fprintf(f,
+                 "  {\"precision\": \"%s\", \"L_padded\": %d, \"rt\": %d, \"k\": %d, \"proposals_per_s\": %.6g, "
+                 "\"measured\": [%s]}%s\n",
+                 v[i].prec.c_str(), v[i].LT, v[i].rt, v[i].k, v[i].rate, v[i].measured.c_str(),
+                 i + 1 < v.size() ? "," : "");
   std::fprintf(f, "]}\n");
   const bool ok = std::fclose(f) == 0;
   return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
@@ -359,6 +393,7 @@ bool write_tune_cache(const std::string& path, const std::vector<TuneEntry>& v) 
 
 struct hfqmc_site {
   int L, LT, RT, n_bins;
+  int DK = 0, K = 1;  // update kind and delay depth of the site's kernel
   size_t off, bytes;  // pool block
   size_t o_desc, o_weiss, o_init, o_fields, o_bins, o_status, o_state, o_force, o_queue;
   bool defined = false, has_state = false;
@@ -516,8 +551,13 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
   const bool tuned = it != c->tune.end();
   if (p.delay == 0 && tuned) {
     pl.k = it->second.k;
-    pl.dk = pl.k > 1 ? dk_delayed : 0;
     pl.rt = it->second.rt;
+    pl.dk = pl.rt == 0 ? 1 : (pl.k > 1 ? dk_delayed : 0);
+  } else if (LT > kMaxRegisterL) {
+    // only the global-memory kernel (fp64 delayed updates) handles these
+    pl.rt = 0;
+    pl.dk = 1;
+    pl.k = p.delay >= 1 ? p.delay : kGlobalMaxDelay;
   } else if (p.delay <= 1) {
     pl.rt = tuned && it->second.k == 1 ? it->second.rt : default_rt(LT, 0);
   } else {
@@ -548,6 +588,8 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws,
   for (int i = 0; i < n; ++i) {
     idx[i] = i;
     plan[i] = force ? *force : plan_for(c, p[i]);
+    if (plan[i].rt == 0 && plan[i].k > kGlobalMaxDelay)
+      return fail(HFQMC_EINVAL, "problem %d: delay %d > %d for L=%d", i, plan[i].k, kGlobalMaxDelay, p[i].L);
     if (!find_kernel(padded_L(p[i].L), plan[i].rt, plan[i].dk))
       return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", i, plan[i].dk ? "delayed-update" : "sweep",
                   p[i].L);
@@ -667,7 +709,7 @@ size_t site_layout(hfqmc_site* s) {
   s->o_bins = off;
   off = align_up(off + sizeof(double) * (size_t)s->n_bins * n_values(s->L), 256);
   s->o_state = off;
-  off = align_up(off + sizeof(double) * 2 * (size_t)s->LT * s->LT, 256);
+  off = align_up(off + state_bytes(s->L), 256);
   s->o_force = off;
   off = align_up(off + 1024 * (sizeof(int32_t) + sizeof(double)), 256);
   s->o_queue = off;  // queue counter + order entry
@@ -684,13 +726,14 @@ void site_offsets(const hfqmc_site* s, ImpDesc& d) {
   d.off_state = (int64_t)(s->off + s->o_state);
   d.off_force = (int64_t)(s->off + s->o_force);
   d.LT = s->LT;
+  d.delay = s->K;
 }
 
 // Launch one work item on a site (blocking, context stream).
 hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d) {
   uint8_t* base = c->pool + s->off;
   site_offsets(s, d);
-  const KernelInfo* k = find_kernel(s->LT, s->RT, 0);
+  const KernelInfo* k = find_kernel(s->LT, s->RT, s->DK);
   if (!k) return fail(HFQMC_EINVAL, "no kernel for LT=%d RT=%d", s->LT, s->RT);
   struct {
     int32_t queue, order;
@@ -706,7 +749,7 @@ hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d) {
 
 // Blocks per CU of a site's kernel (its admission weight is 1 / that).
 int site_bpc(const hfqmc_site* s) {
-  const KernelInfo* k = find_kernel(s->LT, s->RT, 0);
+  const KernelInfo* k = find_kernel(s->LT, s->RT, s->DK);
   int bpc = 0;
   if (!k || kernel_occupancy(k, &bpc) != hipSuccess || bpc < 1) return 1;
   return bpc;
@@ -821,10 +864,12 @@ bool srv_step(hfqmc_ctx* c) {
         break;
       }
     if (slot < 0) break;
-    const int LT = S.ready.front()->site->LT, RT = S.ready.front()->site->RT;
+    const hfqmc_site* head = S.ready.front()->site;
+    const int LT = head->LT, RT = head->RT, DK = head->DK, K = head->K;
     Launch L{slot, {}};
     for (auto it = S.ready.begin(); it != S.ready.end() && (int)L.items.size() < S.max_items;) {
-      if ((*it)->site->LT == LT && (*it)->site->RT == RT) {
+      const hfqmc_site* st = (*it)->site;
+      if (st->LT == LT && st->RT == RT && st->DK == DK && st->K == K) {
         L.items.push_back(*it);
         it = S.ready.erase(it);
       } else {
@@ -842,7 +887,6 @@ bool srv_step(hfqmc_ctx* c) {
       fill_constants(d, r->prob);
       site_offsets(r->site, d);
       d.op = OP_SWEEPS;
-      d.delay = 1;
       const int64_t q = std::max<int64_t>(1, S.quantum / r->site->L);
       r->q = std::min(q, r->total - r->done);
       d.sweep_begin = r->done;
@@ -858,7 +902,7 @@ bool srv_step(hfqmc_ctx* c) {
     *queue = 0;
     uint8_t* dev = c->pool + S.area_off + (size_t)slot * S.slot_bytes;
     const size_t bytes = reinterpret_cast<uint8_t*>(queue + 1) - img;
-    const KernelInfo* k = find_kernel(LT, RT, 0);
+    const KernelInfo* k = find_kernel(LT, RT, DK);
     int bpc = 1;
     hipError_t e = kernel_occupancy(k, &bpc);
     if (e == hipSuccess) e = hipMemcpyAsync(dev, img, bytes, hipMemcpyHostToDevice, S.streams[slot]);
@@ -979,7 +1023,7 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     c->tune_path = tune_cache;
     c->tune_all = read_tune_cache(c->tune_path);
     for (const auto& t : c->tune_all) {
-      const int dk = t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0;
+      const int dk = t.rt == 0 ? 1 : (t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0);
       if (t.prec == prec_name(precision) && t.k >= 1 && t.k <= kMaxDelay && find_kernel(t.LT, t.rt, dk))
         c->tune[t.LT] = t;
     }
@@ -1141,18 +1185,17 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
         props += (int64_t)sweeps * q.L;
       }
     std::vector<Plan> cands;
-    for (int dk : {0, dk_delayed}) {
-      int rts[16];
-      const int nv = std::min(16, kernel_variants(LT, dk, rts, 16));
-      for (int v = 0; v < nv; ++v) {
-        if (dk == 0) {
-          cands.push_back({rts[v], 0, 1});
-        } else {
-          for (int k : {4, 8, 16, 32}) cands.push_back({rts[v], dk, k});
-        }
-      }
-    }
-    TuneEntry best{prec_name(c->prec), LT, 0, 0, -1.0};
+    int rts[16];
+    int nv = std::min(16, kernel_variants(LT, 0, rts, 16));
+    for (int v = 0; v < nv; ++v) cands.push_back({rts[v], 0, 1});
+    nv = std::min(16, kernel_variants(LT, dk_delayed, rts, 16));
+    for (int v = 0; v < nv; ++v)
+      for (int k : {4, 8, 16, 32})
+        if (rts[v] != 0) cands.push_back({rts[v], dk_delayed, k});
+    if (find_kernel(LT, 0, 1))  // the global-memory kernel (fp64 flushes in either precision)
+      for (int k : {4, 8, 16}) cands.push_back({0, 1, k});
+    TuneEntry best{prec_name(c->prec), LT, 0, 0, -1.0, ""};
+    std::string measured;
     for (const Plan& pl : cands) {
       TRY(stage_impl(c, sample.data(), (int)sample.size(), d_ws, ws_bytes, &pl));
       double ms = 1e300;
@@ -1165,8 +1208,12 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
         if (rep > 0) ms = std::min(ms, t);
       }
       const double rate = (double)props / (ms * 1e-3);
-      if (rate > best.rate) best = {prec_name(c->prec), LT, pl.rt, pl.k, rate};
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "%s[%d, %d, %.6g]", measured.empty() ? "" : ", ", pl.rt, pl.k, rate);
+      measured += buf;
+      if (rate > best.rate) best = {prec_name(c->prec), LT, pl.rt, pl.k, rate, ""};
     }
+    best.measured = measured;
     c->tune[LT] = best;
     bool replaced = false;
     for (auto& t : c->tune_all)
@@ -1231,8 +1278,11 @@ hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, hfqmc_site
   s->LT = padded_L(L);
   hfqmc_problem p{};
   p.L = L;
-  p.delay = 1;
-  s->RT = plan_for(c, p).rt;
+  p.delay = 0;
+  const Plan pl = plan_for(c, p);
+  s->RT = pl.rt;
+  s->DK = pl.dk;
+  s->K = pl.k;
   s->n_bins = n_bins;
   s->bytes = site_layout(s);
   if (hfqmc_status st = pool_alloc(c, s->bytes, &s->off)) {
@@ -1390,7 +1440,6 @@ hfqmc_status hfqmc_submit(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p, u
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
   if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
-  if (p->delay > 1) return fail(HFQMC_EINVAL, "serving runs rank-one updates (delay 0 or 1)");
   TRY(validate(*p, 0));
   TRY(srv_start(c));
   Server& S = c->srv;

@@ -7,8 +7,12 @@
 
 namespace hfqmc {
 
-// Largest number of time slices the register-tile kernels handle.
-constexpr int kMaxL = 128;
+// Largest number of time slices: the register-tile kernels handle up to 128,
+// the global-memory kernel up to 160.
+constexpr int kMaxL = 160;
+constexpr int kMaxRegisterL = 128;
+// Panel capacity (largest delay depth) of the global-memory kernel.
+constexpr int kGlobalMaxDelay = 16;
 
 // Operation a work item performs.
 enum Op : int32_t {
@@ -52,7 +56,8 @@ struct alignas(16) ImpDesc {
   int64_t off_fields;       // L int8 fields (in and out)
   int64_t off_bins;         // n_bins x NV doubles: per-bin sums (accumulated)
   int64_t off_status;       // ImpStatus
-  int64_t off_state;        // 2 x LT x LT doubles: G tiles in lane order
+  int64_t off_state;        // 4 x LT x LT doubles: G of both spins (register kernels: tiles in
+                            // lane order; global kernel: row-major), then a drift snapshot
   int64_t off_force;        // OP_FORCE: n_force int32 slices, then n_force doubles ratios
   int64_t off_init;         // F_FIELDS_GIVEN: L int8 initial fields (read only)
   int64_t pad_;

@@ -20,88 +20,9 @@
 // buffered), every lane applies the rank-one update to its tiles.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-#include <utility>
-
-#include "hfqmc_internal.h"
+#include "hfqmc_device.h"
 
 namespace hfqmc {
-
-// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1, so
-// every array index inside f is a constant before any optimisation runs and
-// register arrays can never be demoted to scratch by a run-time index.
-template <class F, int... Is>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
-  (f(std::integral_constant<int, Is>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl(f, std::make_integer_sequence<int, N>{});
-}
-
-// ------------------------------------------------------------- Philox4x64-10
-// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
-// rounds of two 64x64->128 multiplies, Weyl key schedule.
-struct U64x4 {
-  uint64_t v[4];
-};
-
-__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                               uint64_t k0, uint64_t k1) {
-  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
-  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += kW0;
-      k1 += kW1;
-    }
-    const uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
-    const uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
-    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return U64x4{{c0, c1, c2, c3}};
-}
-
-// Purposes of the Philox counter word 2.
-constexpr uint64_t kPurposeInit = 1, kPurposeSweep = 2;
-
-__device__ __forceinline__ double u01(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
-
-// ------------------------------------------------------------- lane helpers
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-template <int JW, typename T>
-__device__ __forceinline__ T pick(const T (&a)[JW], int jj) {
-  T r = a[0];
-  static_for<JW>([&](auto k) __attribute__((always_inline)) {
-    if (k > 0 && jj == k) r = a[k];
-  });
-  return r;
-}
 
 // ------------------------------------------------------------- configuration
 // DK_: 0 = Sherman-Morrison rank-one updates applied to the tiles at once;
@@ -125,15 +46,6 @@ struct Cfg {
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
   static_assert(NTH >= 2 * LT, "measurement needs one thread per (spin, tau_k)");
 };
-
-// Reciprocal to full fp64 precision: hardware estimate plus two Newton steps.
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
 
 template <class C>
 struct Stage {
@@ -761,12 +673,6 @@ __global__ void zero_kernel(uint64_t* __restrict__ p, size_t n) {
 }
 
 // ------------------------------------------------------------- host dispatch
-struct KernelInfo {
-  int LT, RT, DK, threads;
-  size_t lds;
-  const void* fn;
-};
-
 template <int LT, int RT, int DK = 0>
 static KernelInfo info() {
   using C = Cfg<LT, RT, DK>;
@@ -784,15 +690,27 @@ static const KernelInfo kKernels[] = {
 const KernelInfo* find_kernel(int LT, int RT, int DK) {
   for (const auto& k : kKernels)
     if (k.LT == LT && k.RT == RT && k.DK == DK) return &k;
+  const KernelInfo* g = nullptr;
+  const int ng = global_kernels(&g);
+  for (int i = 0; i < ng; ++i)
+    if (g[i].LT == LT && g[i].RT == RT && g[i].DK == DK) return &g[i];
   return nullptr;
 }
 
-// Tile-rows-per-wave variants compiled for (LT, DK); returns their count.
+// Tile-rows-per-wave variants compiled for (LT, DK), 0 standing for the
+// global-memory kernel; returns their count.
 int kernel_variants(int LT, int DK, int* rt_out, int max) {
   int n = 0;
   for (const auto& k : kKernels)
     if (k.LT == LT && k.DK == DK) {
       if (n < max) rt_out[n] = k.RT;
+      ++n;
+    }
+  const KernelInfo* g = nullptr;
+  const int ng = global_kernels(&g);
+  for (int i = 0; i < ng; ++i)
+    if (g[i].LT == LT && g[i].DK == DK) {
+      if (n < max) rt_out[n] = g[i].RT;
       ++n;
     }
   return n;

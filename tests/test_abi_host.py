@@ -48,11 +48,12 @@ def test_site_bytes_grows_with_L():
     b16 = hfqmc.site_bytes(16)
     b64 = hfqmc.site_bytes(64)
     b128 = hfqmc.site_bytes(128)
-    assert b16 < b64 < b128
-    # the Green tiles dominate: 2 x 128 x 128 doubles
-    assert b128 >= 2 * 128 * 128 * 8
+    b160 = hfqmc.site_bytes(160)
+    assert b16 < b64 < b128 < b160
+    # G of both spins plus its drift snapshot dominate: 4 x L x L doubles
+    assert b128 >= 4 * 128 * 128 * 8 and b160 >= 4 * 160 * 160 * 8
     with pytest.raises(hfqmc.HFQMCError):
-        hfqmc.site_bytes(129)
+        hfqmc.site_bytes(161)
     with pytest.raises(hfqmc.HFQMCError):
         hfqmc.site_bytes(0)
 

@@ -42,7 +42,7 @@ def _chain_problem(L, U, mu, beta, seed=21, site=0, n_warmup=10, n_measure=40, n
 
 
 # --------------------------------------------------------------- forced flips
-@pytest.mark.parametrize("L", [1, 5, 16, 20, 40, 64, 80, 96, 128])
+@pytest.mark.parametrize("L", [1, 5, 16, 20, 40, 64, 80, 96, 128, 131, 160])
 def test_forced_flips_match_oracle(ctx, L):
     print(f"forced flips L={L}", flush=True)
     p = _chain_problem(L, U=6.0, mu=0.3, beta=0.25 * L, h=0.2)
@@ -94,7 +94,7 @@ def test_plain_4x4_trajectories(ctx):
 
 def test_uneven_L_batch_trajectories(ctx):
     print("uneven batch", flush=True)
-    Ls = [1, 3, 16, 17, 20, 32, 40, 48, 63, 64, 65, 80, 96, 100, 112, 128]
+    Ls = [1, 3, 16, 17, 20, 32, 40, 48, 63, 64, 65, 80, 96, 100, 112, 128, 129, 150, 160]
     probs = [_chain_problem(L, U=4.0 + 0.5 * i, mu=0.1 * i - 0.5, beta=min(0.2 * L, 10.0), seed=5, site=i,
                             n_warmup=5, n_measure=60, n_bins=6) for i, L in enumerate(Ls)]
     for p in probs[::3]:
@@ -189,9 +189,12 @@ def test_full_size_L64_batch_sampled(ctx):
 def test_invalid_problems_raise(ctx):
     from paper_1006_2716_amd import hfqmc
     p = _chain_problem(16, U=4.0, mu=0.0, beta=4.0)
-    bad = dict(p, L=129, weiss=np.full((2, 129), 0.5))
+    bad = dict(p, L=161, weiss=np.full((2, 161), 0.5))
     with pytest.raises(hfqmc.HFQMCError):
         ctx.solve([bad])
+    big = _chain_problem(150, U=4.0, mu=0.0, beta=10.0)
+    with pytest.raises(hfqmc.HFQMCError):  # device-memory kernel: delay at most 16
+        ctx.solve([dict(big, delay=17)])
     bad = dict(p, n_bins=1)
     with pytest.raises(hfqmc.HFQMCError):
         ctx.solve([bad])

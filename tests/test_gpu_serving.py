@@ -43,7 +43,7 @@ def _problem(L, mu, it=0, seed=31, site=0, sweeps=60, warm=8, n_bins=4):
     H = -A - (mu + 0.02 * it) * np.eye(32)
     g = wl.weiss_from_onebody(H, [16], 0.25 * L, L)[0]
     return dict(L=L, beta=0.25 * L, U=8.0, weiss=np.stack([g, g]), n_warmup=warm, n_measure=sweeps - warm,
-                recompute_every=11, n_bins=n_bins, seed=seed, site=site, sweep_offset=it * sweeps, delay=1)
+                recompute_every=11, n_bins=n_bins, seed=seed, site=site, sweep_offset=it * sweeps, delay=0)
 
 
 def _wait(ctx, tickets, timeout=120.0):
@@ -68,7 +68,7 @@ def _same(x, y):
 
 
 def test_request_alone_and_in_mix_equal_solve(ctx, batch_ctx):
-    Ls = [20, 40, 80, 17, 64, 128, 33, 96]
+    Ls = [20, 40, 80, 17, 64, 128, 33, 96, 160, 150]
     probs = [_problem(L, mu=0.1 * i - 0.3, site=i) for i, L in enumerate(Ls)]
     ref = batch_ctx.solve(probs)
     print("alone", flush=True)
