@@ -14,6 +14,19 @@ Prints ONE JSON line (rank 0).  `value` is proposals/s of the whole job;
 `roofline` prices the sweep kernel's algorithmic fp64 flops against the
 MI355X fp64 vector peak; `cpu_baseline` times the CPU oracle on a bounded
 sample of the same workload on the host cores.
+
+Other workloads (one JSON line each, --workload NAME or all):
+  uneven   512 impurities, L ~ U{32,48,64,96,128}, beta = 8: untuned vs
+           autotuned fp64, and fp32-product delayed updates (k = 8, 16, 32)
+           with their drift and g(tau) shift against the fp64 path
+  serving  Poisson request stream (200/s), L in {20,40,80,160} (4:3:2:1),
+           U = 8, dtau = 0.25, 5000 sweeps, 200 sites x 10 DMFT iterations
+           with device-resident state: p50/p99 latency and throughput
+  trapped  21x21 trap (V0 = 0.05, U = 8, beta = 10, L = 40, AF seed), the
+           325 sites with n > 1e-3, 1000 + 10000 sweeps, fp64
+  slab     41x41 trap (V0 = 0.02, U = 8, beta = 16, L = 80, ~1000 atoms,
+           AF seed), 1281 sites, 1000 + 10000 sweeps; fp64 and fp32-product
+           delayed updates (k = 16)
 """
 from __future__ import annotations
 
@@ -34,15 +47,21 @@ RECOMPUTE_EVERY = 50
 # HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
 # FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
 # valid only for the kernel source with this sha256 prefix.
-PROFILED_KERNEL_SHA = "6dd0dda3d748858e"
-PROFILED_TRAFFIC_BYTES = 1.654e9
+PROFILED_KERNEL_SHA = "c61e9927319b6a81"
+PROFILED_TRAFFIC_BYTES = 1.627e9
+
+
+def kernel_sha() -> str:
+    """sha256 prefix of the register-tile sweep kernel's sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1006_2716_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def kernel_traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_1006_2716_amd", "csrc", "hfqmc_sweep.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    return PROFILED_TRAFFIC_BYTES if sha == PROFILED_KERNEL_SHA else None
+    return PROFILED_TRAFFIC_BYTES if kernel_sha() == PROFILED_KERNEL_SHA else None
 
 
 def algorithmic_flops(L: int, p_acc: float, n_rec: int = RECOMPUTE_EVERY, kbar: float = 0.0) -> float:
@@ -81,8 +100,137 @@ def single_impurity_rate(ctx, probs, n: int = 8):
     return total / t_all
 
 
+def timed_runs(ctx, steps, warmup, graph=False):
+    """Run the staged batch; returns (wall ms per step, per-step ms list,
+    per-step kernel ms of launch 0 or of the whole pass)."""
+    import torch
+    run = ctx.run_graph if graph else ctx.run
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    step_ms, kern_ms = [], []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        kern_ms.append(ctx.last_run_ms()[0] if graph else ctx.last_launch_ms(0)[0])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t_start) * 1e3 / steps, step_ms, kern_ms
+
+
+def _line(metric, value, unit, steps, warmup, ms, config, dtype="f64", **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def _g_shift(a, b):
+    """max |g_a - g_b| and max |g_a - g_b| / sigma_comb over tau, spins, impurities."""
+    dmax, zmax = 0.0, 0.0
+    for x, y in zip(a, b):
+        for s in ("up", "dn"):
+            d = np.abs(x[f"g_{s}"] - y[f"g_{s}"])
+            e = np.sqrt(x[f"g_{s}_err"] ** 2 + y[f"g_{s}_err"] ** 2)
+            dmax = max(dmax, float(d.max()))
+            zmax = max(zmax, float((d[e > 0] / e[e > 0]).max()))
+    return dmax, zmax
+
+
+def bench_uneven(args):
+    import torch
+    from paper_1006_2716_amd import hfqmc, workloads
+    probs = workloads.chain_batch(n_imp=512, Ls=(32, 48, 64, 96, 128), seed=3)
+    props = sum((p["n_warmup"] + p["n_measure"]) * p["L"] for p in probs)
+    ctx = hfqmc.Context(0)
+    ws = ctx.alloc_workspace(probs)
+    ctx.stage(probs, ws)
+    ms_def, _, _ = timed_runs(ctx, args.steps, args.warmup)
+    ref = ctx.collect()
+    t0 = time.perf_counter()
+    ctx.tune(probs, sweeps=64, workspace=ws)
+    tune_s = time.perf_counter() - t0
+    plans = {L: ctx.plan(L, 0)[:2] for L in (32, 48, 64, 96, 128)}
+    ctx.stage(probs, ws)
+    ms_tuned, step_ms, _ = timed_runs(ctx, args.steps, args.warmup)
+    launches = [ctx.last_launch_ms(i) for i in range(ctx.last_run_ms()[1])]
+    mixed = {}
+    mctx = hfqmc.Context(0, precision=hfqmc.MIXED)
+    for k in (8, 16, 32):
+        pk = [dict(p, delay=k) for p in probs]
+        mctx.stage(pk, ws)
+        ms_k, _, _ = timed_runs(mctx, 1, 0)
+        rk = mctx.collect()
+        dmax, zmax = _g_shift(rk, ref)
+        mixed[str(k)] = dict(proposals_per_s=props / (ms_k * 1e-3), ms=ms_k,
+                             max_drift=max(r["max_drift"] for r in rk), max_g_shift_vs_fp64=dmax,
+                             max_g_shift_sigma=zmax)
+    torch.cuda.synchronize()
+    _line("HF-QMC spin-flip proposals/s (batched impurities, uneven L)", props / (ms_tuned * 1e-3), "proposals/s",
+          args.steps, args.warmup, ms_tuned,
+          {"workload": "512 impurities, L~U{32,48,64,96,128}, beta=8, U~U[4,12], open 64-site chain centre-site "
+                       "Weiss at mu_eff~U[-1,1] (seed 3), 200+2000 sweeps, fp64, autotuned shapes",
+           "proposals_per_step": props, "untuned_proposals_per_s": props / (ms_def * 1e-3),
+           "tune_seconds": round(tune_s, 2), "plan_rt_k_by_L": {str(L): v for L, v in plans.items()},
+           "class_launch_ms_L_items": launches},
+          p99_solve_ms=float(np.percentile(step_ms, 99)), mixed_delayed=mixed)
+
+
+def bench_serving(args):
+    from paper_1006_2716_amd import hfqmc, serve_load, workloads
+    sites, arrivals, weiss = workloads.serving_requests()
+    ctx = hfqmc.Context(0)
+    ctx.attach_pool(1 << 30)
+    t0 = time.perf_counter()
+    out = serve_load.replay(ctx, sites, arrivals, weiss, n_iter=10, sweeps=5000, warm_first=500, warm_next=100,
+                            progress=lambda m: print(m, file=sys.stderr, flush=True))
+    wall = time.perf_counter() - t0
+    st = ctx.serve_stats()
+    ctx.close()
+    out.pop("results")
+    _line("HF-QMC serving: p99 request latency (Poisson 200 req/s)", out["p99_ms"], "ms", 1, 0, wall * 1e3,
+          {"workload": "Poisson 200 req/s, L in {20,40,80,160} weights 4:3:2:1, U=8, dtau=0.25, 5000 sweeps "
+                       "(500 warm-up first, 100 later), 200 sites x 10 DMFT iterations, state on device",
+           "quantum_proposals": 16384, "launches": st["launches"]},
+          higher_is_better=False, serving=out)
+
+
+def bench_lattice(args, name):
+    from paper_1006_2716_amd import hfqmc, workloads
+    if name == "trapped":
+        probs = workloads.trapped_21x21()
+        legs = [("fp64", hfqmc.FP64, 0)]
+        desc = "21x21 trap V0=0.05, U=8, beta=10, L=40, AF seed h=0.1, 325 sites n>1e-3, 1000+10000 sweeps"
+    else:
+        probs = workloads.slab_41x41()
+        legs = [("fp64", hfqmc.FP64, 0), ("mixed_k16", hfqmc.MIXED, 16)]
+        desc = "41x41 trap V0=0.02, U=8, beta=16, L=80, mu_eff for ~1000 atoms, AF seed, 1281 sites, 1000+10000 sweeps"
+    props = sum((p["n_warmup"] + p["n_measure"]) * p["L"] for p in probs)
+    res = {}
+    ref = None
+    for leg, prec, k in legs:
+        ctx = hfqmc.Context(0, precision=prec)
+        pk = [dict(p, delay=k) for p in probs]
+        ctx.stage(pk)
+        ms, _, _ = timed_runs(ctx, 1, 0)
+        r = ctx.collect()
+        res[leg] = dict(proposals_per_s=props / (ms * 1e-3), ms=ms, max_drift=max(x["max_drift"] for x in r),
+                        atoms=float(sum(x["n_up"] + x["n_dn"] for x in r)))
+        if ref is None:
+            ref = r
+        else:
+            res[leg]["max_g_shift_vs_fp64"], res[leg]["max_g_shift_sigma"] = _g_shift(r, ref)
+        ctx.close()
+    _line(f"HF-QMC spin-flip proposals/s ({name} lattice)", res["fp64"]["proposals_per_s"], "proposals/s", 1, 0,
+          res["fp64"]["ms"], {"workload": desc, "n_impurities": len(probs), "proposals": props}, legs=res)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -109,6 +257,17 @@ def main():
         print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a design "
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
+    if args.workload != "headline":
+        names = ["uneven", "serving", "trapped", "slab"] if args.workload == "all" else [args.workload]
+        for n in names:
+            print(f"== {n}", file=sys.stderr, flush=True)
+            if n == "uneven":
+                bench_uneven(args)
+            elif n == "serving":
+                bench_serving(args)
+            else:
+                bench_lattice(args, n)
+        return
 
     import torch
     from paper_1006_2716_amd import hfqmc, workloads
@@ -122,30 +281,15 @@ def main():
     ws = ctx.alloc_workspace(probs)
     ctx.stage(probs, ws)
     rt, k, _ = ctx.plan(L, args.delay)
-    run = ctx.run_graph if args.graph else ctx.run
-
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-
-    step_ms, kern_ms = [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        run()
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
-        # the sweep kernel's own events (the whole pass when replayed from a graph)
-        kern_ms.append(ctx.last_run_ms()[0] if args.graph else ctx.last_launch_ms(0)[0])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    # kernel time from the sweep kernel's own events (the whole pass when
+    # replayed from a graph)
+    ms_per_step, step_ms, kern_ms = timed_runs(ctx, args.steps, args.warmup, graph=args.graph)
 
     res = ctx.collect()
     proposals = sum(r["proposals"] for r in res)
     accepts = sum(r["accepts"] for r in res)
     assert all(r["status"] == 0 for r in res), "non-finite result"
     p_acc = accepts / proposals
-    ms_per_step = elapsed * 1e3 / args.steps
     value = proposals / (ms_per_step * 1e-3)
 
     kbar = 0.0 if k <= 1 else (k - 1) / 2.0  # mean pending updates while appending
