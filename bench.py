@@ -184,6 +184,7 @@ def bench_serving(args):
     sites, arrivals, weiss = workloads.serving_requests()
     ctx = hfqmc.Context(0)
     ctx.attach_pool(1 << 30)
+    ctx.serve_config(step_ms=args.step_ms, quantum_proposals=args.quantum)
     t0 = time.perf_counter()
     out = serve_load.replay(ctx, sites, arrivals, weiss, n_iter=10, sweeps=5000, warm_first=500, warm_next=100,
                             progress=lambda m: print(m, file=sys.stderr, flush=True))
@@ -194,7 +195,8 @@ def bench_serving(args):
     _line("HF-QMC serving: p99 request latency (Poisson 200 req/s)", out["p99_ms"], "ms", 1, 0, wall * 1e3,
           {"workload": "Poisson 200 req/s, L in {20,40,80,160} weights 4:3:2:1, U=8, dtau=0.25, 5000 sweeps "
                        "(500 warm-up first, 100 later), 200 sites x 10 DMFT iterations, state on device",
-           "quantum_proposals": 16384, "launches": st["launches"]},
+           "step_ms": args.step_ms, "quantum_proposals": args.quantum, "steps": st["steps"],
+           "launches": st["launches"], "step_ms_avg": st["step_ms_avg"], "launch_ms_avg": st["launch_ms_avg"]},
           higher_is_better=False, serving=out)
 
 
@@ -240,6 +242,8 @@ def main():
                     help="update depth: 1 rank-one (default, measured fastest), 2..32 delayed rank-k")
     ap.add_argument("--mixed", action="store_true", help="fp32 delayed-update products (with --delay > 1)")
     ap.add_argument("--graph", action="store_true", help="replay the pass from a captured hipGraph")
+    ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
+    ap.add_argument("--quantum", type=int, default=0, help="serving: fixed proposals per request per step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()

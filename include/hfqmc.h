@@ -209,21 +209,25 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drif
 /* ---- serving: continuous batching of impurity solves on sites ----
  * A library thread admits submitted requests while the CU shares of the
  * admitted ones (1 / resident workgroups per CU of the site's kernel) fit
- * the capacity, and advances every admitted request in launches of about
- * `quantum_proposals` proposals each; requests that arrive while others run
- * start in the next free launch slot, and launches of different kernel
- * classes run concurrently.  Field and G state stay on the device: a request
- * without init_fields on a site that already ran starts from the site's last
- * fields with a fresh Dyson solve (the next DMFT iteration), otherwise from
- * init_fields or drawn fields.  A request's result is bitwise the result of
- * hfqmc_solve on the same problem with delay 0, whatever else runs beside
- * it: a site runs the kernel shape its L had (tuned or default) when it was
- * opened, whatever the request's delay field.  The site must not be used by the
- * test hooks while it has a request (EAGAIN). */
+ * the capacity, and advances all admitted requests together in steps: a
+ * step launches every admitted request once, each kernel class on its own
+ * stream (classes run concurrently), with a per-class sweep count sized from
+ * the class's time per proposal (a cost model of the kernel shape, measured
+ * on MI355X) so that the step takes about `step_ms`.  Requests that arrive
+ * while a step runs join the next step.
+ * Field and G state stay on the device: a request without init_fields on a
+ * site that already ran starts from the site's last fields with a fresh
+ * Dyson solve (the next DMFT iteration), otherwise from init_fields or drawn
+ * fields.  A request's result is bitwise the result of hfqmc_solve on the
+ * same problem with delay 0, whatever else runs beside it and however it is
+ * split into steps: a site runs the kernel shape its L had (tuned or
+ * default) when it was opened, whatever the request's delay field.  The
+ * site must not be used by the test hooks while it has a request (EAGAIN). */
 
-/* quantum_proposals >= 1 (default 16384); capacity_cus > 0 sets the
- * admission capacity in CUs (default: all CUs), 0 keeps the default. */
-hfqmc_status hfqmc_serve_config(hfqmc_ctx *ctx, int64_t quantum_proposals, double capacity_cus);
+/* step_ms > 0 (default 8) sets the target step duration; quantum_proposals
+ * > 0 instead fixes the proposals per request per step (0: timed steps);
+ * capacity_cus > 0 sets the admission capacity in CUs (0: all CUs). */
+hfqmc_status hfqmc_serve_config(hfqmc_ctx *ctx, double step_ms, int64_t quantum_proposals, double capacity_cus);
 /* Queue a request on a site (problem L and n_bins must match the site's).
  * Inputs are copied before the call returns.  EAGAIN: the site has a
  * request in progress, or the queue is full.  *ticket identifies it. */
@@ -237,11 +241,13 @@ hfqmc_status hfqmc_poll(hfqmc_ctx *ctx, uint64_t ticket, hfqmc_result *out);
 hfqmc_status hfqmc_cancel(hfqmc_ctx *ctx, uint64_t ticket);
 
 typedef struct {
-    int64_t submitted, completed, cancelled, launches;
+    int64_t submitted, completed, cancelled, launches, steps;
     int32_t pending;        /* queued, not admitted */
     int32_t active;         /* admitted, waiting for or in a launch */
     double capacity_used;   /* CU shares held by admitted requests */
     double capacity;
+    double step_ms_avg;     /* wall time of a step, launch to retirement */
+    double launch_ms_avg;   /* device time of one class launch (HIP events) */
 } hfqmc_serve_stats_t;
 hfqmc_status hfqmc_serve_stats(hfqmc_ctx *ctx, hfqmc_serve_stats_t *out);
 

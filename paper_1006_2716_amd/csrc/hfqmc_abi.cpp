@@ -421,8 +421,15 @@ struct Request {
 
 struct Launch {
   int slot;
+  int LT, RT, DK, K;  // kernel class
+  int64_t max_props;  // largest q * L among the items (the launch's critical path)
   std::vector<Request*> items;
 };
+
+// Kernel class key of a site.
+inline int64_t class_key(const hfqmc_site* s) {
+  return ((int64_t)s->LT << 24) | ((int64_t)(s->RT & 0xff) << 16) | ((int64_t)s->DK << 8) | s->K;
+}
 
 struct Server {
   std::thread th;
@@ -432,21 +439,23 @@ struct Server {
   std::string error;
   std::deque<Request*> pending;
   std::vector<Request*> ready;
-  std::vector<Launch> inflight;
+  std::vector<Launch> inflight;  // the classes of the step in flight
   std::map<uint64_t, Request*> tickets;
   uint64_t next_ticket = 1;
   double used = 0.0;
   double capacity = 0.0;      // CU shares available to admitted requests
-  int64_t quantum = 16384;    // proposals per request per launch
-  int max_items = 2048;       // requests per launch
+  double step_ms = 8.0;       // target duration of one step
+  int64_t quantum = 0;        // > 0: fixed proposals per request per step instead
+  int max_items = 2048;       // requests per class launch
   size_t max_pending = 1 << 16;
   hipStream_t streams[kSrvStreams] = {};
-  hipEvent_t events[kSrvStreams] = {};
-  bool slot_busy[kSrvStreams] = {};
+  hipEvent_t ev_begin[kSrvStreams] = {}, ev_end[kSrvStreams] = {};
   hipStream_t io = nullptr;
   size_t area_off = 0, area_bytes = 0, slot_bytes = 0;
   uint8_t* host_img[kSrvStreams] = {};
-  int64_t submitted = 0, completed = 0, cancelled = 0, launches = 0;
+  int64_t submitted = 0, completed = 0, cancelled = 0, launches = 0, steps = 0;
+  double step_ms_sum = 0.0, kernel_ms_sum = 0.0;  // wall time of steps, device time of class launches
+  std::chrono::steady_clock::time_point step_t0;
 };
 
 }  // namespace
@@ -782,54 +791,72 @@ hfqmc_status srv_finish(hfqmc_ctx* c, Request* r) {
   return HFQMC_OK;
 }
 
-// One pass of the engine: retire finished launches, admit, launch.  Returns
-// true when anything is in flight.
+// Time per proposal of one chain of a kernel class, as measured on MI355X
+// with about one impurity per CU: ~0.75 us for the register-tile kernels up
+// to L = 64, growing about linearly in L beyond, ~3 us at L = 160 for the
+// device-memory kernel.  Used to give every class about `step_ms` of work
+// per step.
+double model_us_per_proposal(const hfqmc_site* s) {
+  if (s->RT == 0) return 3.0 * s->L / 160.0;
+  return 0.75 * (s->L > 64 ? s->L / 64.0 : 1.0);
+}
+
+// One pass of the engine.  Work advances in lockstep steps: a step launches
+// every admitted request once, each kernel class on its own stream, with a
+// per-class sweep count sized from that class's measured time per proposal
+// so that every class kernel takes about `step_ms`.  When all kernels of the
+// step have finished, its requests retire or become ready again, queued
+// requests are admitted, and the next step starts.  Returns true while a
+// step is in flight.
 bool srv_step(hfqmc_ctx* c) {
   Server& S = c->srv;
   auto device_fail = [&](const char* what, hipError_t e) {
     S.failed = true;
     S.error = std::string(what) + ": " + hipGetErrorString(e);
   };
-  // 1. retire
-  for (size_t i = 0; i < S.inflight.size();) {
-    Launch& L = S.inflight[i];
-    const hipError_t q = hipEventQuery(S.events[L.slot]);
-    if (q == hipErrorNotReady) {
-      ++i;
-      continue;
+  // 1. retire the step once every class kernel of it has finished
+  if (!S.inflight.empty()) {
+    for (const Launch& L : S.inflight) {
+      const hipError_t q = hipEventQuery(S.ev_end[L.slot]);
+      if (q == hipErrorNotReady) return true;
+      if (q != hipSuccess) device_fail("hipEventQuery", q);
     }
-    if (q != hipSuccess) device_fail("hipEventQuery", q);
-    for (Request* r : L.items) {
-      r->done += r->q;
-      r->first = false;
-      r->q = 0;
-      if (r->cancel) {
-        S.used -= r->weight;
-        r->site->busy = false;
-        r->site->has_state = true;
-        S.tickets.erase(r->ticket);
-        ++S.cancelled;
-        delete r;
-      } else if (S.failed || r->done >= r->total) {
-        S.used -= r->weight;
-        if (S.failed) {
-          r->status = HFQMC_EDEVICE;
-        } else if (srv_finish(c, r) != HFQMC_OK) {
-          S.failed = true;
-          S.error = t_err;
-          r->status = HFQMC_EDEVICE;
+    S.step_ms_sum += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - S.step_t0).count();
+    for (Launch& L : S.inflight) {
+      float ms = 0.f;
+      if (!S.failed && hipEventElapsedTime(&ms, S.ev_begin[L.slot], S.ev_end[L.slot]) == hipSuccess)
+        S.kernel_ms_sum += ms;
+      for (Request* r : L.items) {
+        r->done += r->q;
+        r->first = false;
+        r->q = 0;
+        if (r->cancel) {
+          S.used -= r->weight;
+          r->site->busy = false;
+          r->site->has_state = true;
+          S.tickets.erase(r->ticket);
+          ++S.cancelled;
+          delete r;
+        } else if (S.failed || r->done >= r->total) {
+          S.used -= r->weight;
+          if (S.failed) {
+            r->status = HFQMC_EDEVICE;
+          } else if (srv_finish(c, r) != HFQMC_OK) {
+            S.failed = true;
+            S.error = t_err;
+            r->status = HFQMC_EDEVICE;
+          }
+          r->state = R_DONE;
+          r->site->busy = false;
+          r->site->has_state = true;
+          ++S.completed;
+        } else {
+          r->state = R_READY;
+          S.ready.push_back(r);
         }
-        r->state = R_DONE;
-        r->site->busy = false;
-        r->site->has_state = true;
-        ++S.completed;
-      } else {
-        r->state = R_READY;
-        S.ready.push_back(r);
       }
     }
-    S.slot_busy[L.slot] = false;
-    S.inflight.erase(S.inflight.begin() + i);
+    S.inflight.clear();
   }
   if (S.failed) {
     for (Request* r : S.ready) {
@@ -839,9 +866,9 @@ bool srv_step(hfqmc_ctx* c) {
       r->site->busy = false;
     }
     S.ready.clear();
-    return !S.inflight.empty();
+    return false;
   }
-  if (S.stop) return !S.inflight.empty();
+  if (S.stop) return false;
   // 2. admit in arrival order; a request that does not fit lets smaller
   // later ones pass
   for (auto it = S.pending.begin(); it != S.pending.end();) {
@@ -855,40 +882,40 @@ bool srv_step(hfqmc_ctx* c) {
       ++it;
     }
   }
-  // 3. launch: one kernel class per free stream, its ready requests together
-  while (!S.ready.empty()) {
-    int slot = -1;
-    for (int k = 0; k < kSrvStreams; ++k)
-      if (!S.slot_busy[k]) {
-        slot = k;
-        break;
-      }
-    if (slot < 0) break;
-    const hfqmc_site* head = S.ready.front()->site;
-    const int LT = head->LT, RT = head->RT, DK = head->DK, K = head->K;
-    Launch L{slot, {}};
-    for (auto it = S.ready.begin(); it != S.ready.end() && (int)L.items.size() < S.max_items;) {
-      const hfqmc_site* st = (*it)->site;
-      if (st->LT == LT && st->RT == RT && st->DK == DK && st->K == K) {
-        L.items.push_back(*it);
-        it = S.ready.erase(it);
-      } else {
-        ++it;
-      }
+  if (S.ready.empty()) return false;
+  // 3. the next step: one launch per kernel class
+  std::map<int64_t, std::vector<Request*>> classes;
+  for (Request* r : S.ready) classes[class_key(r->site)].push_back(r);
+  std::vector<Request*> left;
+  int slot = 0;
+  for (auto& kv : classes) {
+    std::vector<Request*>& v = kv.second;
+    if (slot == kSrvStreams) {  // more classes than streams: the rest waits a step
+      left.insert(left.end(), v.begin(), v.end());
+      continue;
     }
-    const int n = (int)L.items.size();
+    if ((int)v.size() > S.max_items) {
+      left.insert(left.end(), v.begin() + S.max_items, v.end());
+      v.resize(S.max_items);
+    }
+    const hfqmc_site* head = v.front()->site;
+    Launch L{slot, head->LT, head->RT, head->DK, head->K, 0, v};
+    const double us = model_us_per_proposal(head);
+    const int n = (int)v.size();
     uint8_t* img = S.host_img[slot];
     ImpDesc* descs = reinterpret_cast<ImpDesc*>(img);
     int32_t* order = reinterpret_cast<int32_t*>(img + align_up(sizeof(ImpDesc) * S.max_items, 256));
     int32_t* queue = order + S.max_items;
     for (int i = 0; i < n; ++i) {
-      Request* r = L.items[i];
+      Request* r = v[i];
       ImpDesc d{};
       fill_constants(d, r->prob);
       site_offsets(r->site, d);
       d.op = OP_SWEEPS;
-      const int64_t q = std::max<int64_t>(1, S.quantum / r->site->L);
+      const int64_t props = S.quantum > 0 ? S.quantum : (int64_t)(1e3 * S.step_ms / us);
+      const int64_t q = std::max<int64_t>(1, props / r->site->L);
       r->q = std::min(q, r->total - r->done);
+      L.max_props = std::max(L.max_props, r->q * r->site->L);
       d.sweep_begin = r->done;
       d.sweep_end = r->done + r->q;
       if (r->first)
@@ -902,21 +929,25 @@ bool srv_step(hfqmc_ctx* c) {
     *queue = 0;
     uint8_t* dev = c->pool + S.area_off + (size_t)slot * S.slot_bytes;
     const size_t bytes = reinterpret_cast<uint8_t*>(queue + 1) - img;
-    const KernelInfo* k = find_kernel(LT, RT, DK);
+    const KernelInfo* k = find_kernel(L.LT, L.RT, L.DK);
     int bpc = 1;
     hipError_t e = kernel_occupancy(k, &bpc);
     if (e == hipSuccess) e = hipMemcpyAsync(dev, img, bytes, hipMemcpyHostToDevice, S.streams[slot]);
+    if (e == hipSuccess) e = hipEventRecord(S.ev_begin[slot], S.streams[slot]);
     if (e == hipSuccess)
       e = launch_sweep(k, std::min(n, std::max(1, bpc) * c->n_cu), S.streams[slot], reinterpret_cast<const ImpDesc*>(dev),
                        reinterpret_cast<const int32_t*>(dev + (reinterpret_cast<uint8_t*>(order) - img)), n,
                        reinterpret_cast<int*>(dev + (reinterpret_cast<uint8_t*>(queue) - img)), c->pool);
-    if (e == hipSuccess) e = hipEventRecord(S.events[slot], S.streams[slot]);
+    if (e == hipSuccess) e = hipEventRecord(S.ev_end[slot], S.streams[slot]);
     if (e != hipSuccess) device_fail("serving launch", e);
-    S.slot_busy[slot] = true;
     S.inflight.push_back(std::move(L));
     ++S.launches;
+    ++slot;
   }
-  return !S.inflight.empty();
+  S.ready.swap(left);
+  ++S.steps;
+  S.step_t0 = std::chrono::steady_clock::now();
+  return true;
 }
 
 void srv_main(hfqmc_ctx* c) {
@@ -944,7 +975,8 @@ hfqmc_status srv_start(hfqmc_ctx* c) {
   TRY(pool_alloc(c, S.area_bytes, &S.area_off));
   for (int k = 0; k < kSrvStreams; ++k) {
     HIP_TRY(hipStreamCreateWithFlags(&S.streams[k], hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&S.events[k], hipEventDisableTiming));
+    HIP_TRY(hipEventCreate(&S.ev_begin[k]));
+    HIP_TRY(hipEventCreate(&S.ev_end[k]));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&S.host_img[k]), S.slot_bytes, hipHostMallocDefault));
   }
   HIP_TRY(hipStreamCreateWithFlags(&S.io, hipStreamNonBlocking));
@@ -970,7 +1002,8 @@ void srv_shutdown(hfqmc_ctx* c) {
   S.ready.clear();
   for (int k = 0; k < kSrvStreams; ++k) {
     (void)hipStreamDestroy(S.streams[k]);
-    (void)hipEventDestroy(S.events[k]);
+    (void)hipEventDestroy(S.ev_begin[k]);
+    (void)hipEventDestroy(S.ev_end[k]);
     (void)hipHostFree(S.host_img[k]);
   }
   (void)hipStreamDestroy(S.io);
@@ -1427,9 +1460,11 @@ hfqmc_status hfqmc_site_get_fields(hfqmc_ctx* c, hfqmc_site* s, int8_t* fields) 
 
 // ---------------------------------------------------------------- serving
 
-hfqmc_status hfqmc_serve_config(hfqmc_ctx* c, int64_t quantum_proposals, double capacity_cus) {
-  if (!c || quantum_proposals < 1 || capacity_cus < 0) return fail(HFQMC_EINVAL, "hfqmc_serve_config: bad arguments");
+hfqmc_status hfqmc_serve_config(hfqmc_ctx* c, double step_ms, int64_t quantum_proposals, double capacity_cus) {
+  if (!c || !(step_ms > 0) || quantum_proposals < 0 || capacity_cus < 0)
+    return fail(HFQMC_EINVAL, "hfqmc_serve_config: bad arguments");
   std::lock_guard<std::mutex> g(c->srv.mu);
+  c->srv.step_ms = step_ms;
   c->srv.quantum = quantum_proposals;
   c->srv.capacity = capacity_cus > 0 ? capacity_cus : (double)c->n_cu;
   return HFQMC_OK;
@@ -1549,6 +1584,9 @@ hfqmc_status hfqmc_serve_stats(hfqmc_ctx* c, hfqmc_serve_stats_t* out) {
   out->completed = S.completed;
   out->cancelled = S.cancelled;
   out->launches = S.launches;
+  out->steps = S.steps;
+  out->step_ms_avg = S.steps ? S.step_ms_sum / (double)S.steps : 0.0;
+  out->launch_ms_avg = S.launches ? S.kernel_ms_sum / (double)S.launches : 0.0;
   out->pending = (int32_t)S.pending.size();
   int32_t inflight = 0;
   for (const auto& L : S.inflight) inflight += (int32_t)L.items.size();

@@ -128,12 +128,16 @@ struct EngineG {
         (v == 0 ? P.pa : P.pb)[s][kb][i] = 0.0;
       } else if (v == 0) {
         double x = Gs[(size_t)i * LT + l];
-        for (int j = 0; j < kb; ++j) x = __builtin_fma(P.pa[s][j][i], P.pb[s][j][l], x);
+#pragma unroll
+        for (int j = 0; j < KP; ++j)  // unrolled: all panel reads issue at once
+          if (j < kb) x = __builtin_fma(P.pa[s][j][i], P.pb[s][j][l], x);
         if (i == l) x -= 1.0;
         P.pa[s][kb][i] = (s ? fd : fu) * x;
       } else {
         double x = Gs[(size_t)l * LT + i];
-        for (int j = 0; j < kb; ++j) x = __builtin_fma(P.pa[s][j][l], P.pb[s][j][i], x);
+#pragma unroll
+        for (int j = 0; j < KP; ++j)
+          if (j < kb) x = __builtin_fma(P.pa[s][j][l], P.pb[s][j][i], x);
         P.pb[s][kb][i] = x;
       }
     }
@@ -149,24 +153,33 @@ struct EngineG {
   }
 
   // G0 += A B^T, four pending updates per matrix-core step.  Wave w takes
-  // tiles w, w + NW, ...; U tiles at a time so their loads overlap.  Lane
-  // (q, c) = (lane / 16, lane % 16) holds tile row 4 r + q, column c in
-  // accumulator register r, and feeds A[row c][k0 + q], B[k0 + q][col c].
+  // tiles w, w + NW, ... in groups of U; the loads of the next group are in
+  // flight while the matrix cores work on the current one.  Lane (q, c) =
+  // (lane / 16, lane % 16) holds tile row 4 r + q, column c in accumulator
+  // register r, and feeds A[row c][k0 + q], B[k0 + q][col c].
+  __device__ __forceinline__ double* tile_ptr(int t, int q, int c) const {
+    const int s = t / (NT * NT), ti = (t / NT) % NT, tj = t % NT;
+    return gm + (size_t)s * LT * LT + (size_t)(16 * ti + q) * LT + 16 * tj + c;
+  }
+
   __device__ __forceinline__ void flush() {
     if (kb == 0) return;
     const auto& P = sm.u.p;
     const int q = lane >> 4, c = lane & 15;
-    constexpr int NTILE = 2 * NT * NT, U = 4;
-    for (int t0 = wave; t0 < NTILE; t0 += C::NW * U) {
-      d4 acc[U];
-      double* gp[U];
+    constexpr int NTILE = 2 * NT * NT, U = 4, STEP = C::NW * U;
+    d4 cur[U], nxt[U];
+    auto load = [&](int t0, d4 (&acc)[U]) __attribute__((always_inline)) {
       static_for<U>([&](auto u) __attribute__((always_inline)) {
         const int t = t0 + u * C::NW;
-        const int tt = t < NTILE ? t : t0;
-        const int s = tt / (NT * NT), ti = (tt / NT) % NT, tj = tt % NT;
-        gp[u] = gm + (size_t)s * LT * LT + (size_t)(16 * ti + q) * LT + 16 * tj + c;
-        acc[u] = d4{gp[u][0], gp[u][4 * LT], gp[u][8 * LT], gp[u][12 * LT]};
+        if (t < NTILE) {
+          const double* g = tile_ptr(t, q, c);
+          acc[u] = d4{g[0], g[4 * LT], g[8 * LT], g[12 * LT]};
+        }
       });
+    };
+    if (wave < NTILE) load(wave, cur);
+    for (int t0 = wave; t0 < NTILE; t0 += STEP) {
+      if (t0 + STEP < NTILE) load(t0 + STEP, nxt);
       for (int k0 = 0; k0 < kb; k0 += 4) {
         const int k = k0 + q;
         static_for<U>([&](auto u) __attribute__((always_inline)) {
@@ -175,16 +188,19 @@ struct EngineG {
           const int s = tt / (NT * NT), ti = (tt / NT) % NT, tj = tt % NT;
           const double av = k < kb ? P.pa[s][k][16 * ti + c] : 0.0;
           const double bv = k < kb ? P.pb[s][k][16 * tj + c] : 0.0;
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+          cur[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cur[u], 0, 0, 0);
         });
       }
       static_for<U>([&](auto u) __attribute__((always_inline)) {
-        if (t0 + u * C::NW < NTILE) {
-          gp[u][0] = acc[u][0];
-          gp[u][4 * LT] = acc[u][1];
-          gp[u][8 * LT] = acc[u][2];
-          gp[u][12 * LT] = acc[u][3];
+        const int t = t0 + u * C::NW;
+        if (t < NTILE) {
+          double* g = tile_ptr(t, q, c);
+          g[0] = cur[u][0];
+          g[4 * LT] = cur[u][1];
+          g[8 * LT] = cur[u][2];
+          g[12 * LT] = cur[u][3];
         }
+        cur[u] = nxt[u];
       });
     }
     publish();  // also frees the panels

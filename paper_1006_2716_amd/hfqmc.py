@@ -51,7 +51,9 @@ class Result(C.Structure):
 class ServeStats(C.Structure):
     _fields_ = [
         ("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64), ("launches", C.c_int64),
+        ("steps", C.c_int64),
         ("pending", C.c_int32), ("active", C.c_int32), ("capacity_used", C.c_double), ("capacity", C.c_double),
+        ("step_ms_avg", C.c_double), ("launch_ms_avg", C.c_double),
     ]
 
 
@@ -92,7 +94,7 @@ def lib():
             "hfqmc_tune": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t, C.c_int32],
             "hfqmc_plan": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                            C.POINTER(C.c_double)],
-            "hfqmc_serve_config": [_VP, C.c_int64, C.c_double],
+            "hfqmc_serve_config": [_VP, C.c_double, C.c_int64, C.c_double],
             "hfqmc_submit": [_VP, _VP, C.POINTER(Problem), C.POINTER(C.c_uint64)],
             "hfqmc_poll": [_VP, C.c_uint64, C.POINTER(Result)],
             "hfqmc_cancel": [_VP, C.c_uint64],
@@ -290,8 +292,9 @@ class Context:
         return rt.value, k.value, rate.value
 
     # ---------------------------------------------------------------- serving
-    def serve_config(self, quantum_proposals: int = 16384, capacity_cus: float = 0.0):
-        _check(lib().hfqmc_serve_config(self.h, int(quantum_proposals), float(capacity_cus)), "hfqmc_serve_config")
+    def serve_config(self, step_ms: float = 8.0, quantum_proposals: int = 0, capacity_cus: float = 0.0):
+        _check(lib().hfqmc_serve_config(self.h, float(step_ms), int(quantum_proposals), float(capacity_cus)),
+               "hfqmc_serve_config")
 
     def submit(self, site: "Site", problem) -> int | None:
         """Queue a request; returns its ticket, or None if not admissible now (EAGAIN)."""

@@ -18,7 +18,7 @@ def site_request(site: dict, it: int, weiss, sweeps: int, warm_first: int, warm_
     nw = warm_first if it == 0 else warm_next
     return dict(L=site["L"], beta=site["beta"], U=site["U"], weiss=weiss(site, it), n_warmup=nw,
                 n_measure=sweeps - nw, recompute_every=50, n_bins=n_bins, seed=site["seed"], site=site["site"],
-                sweep_offset=it * sweeps, delay=1)
+                sweep_offset=it * sweeps, delay=0)
 
 
 def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, warm_first: int = 500,

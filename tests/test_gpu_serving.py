@@ -155,10 +155,23 @@ def test_busy_site_and_cancel(ctx):
     s.close()
 
 
-def test_replay_small_stream(ctx):
-    sites, arrivals, weiss = wl.serving_requests(n_sites=12, n_iter=3, rate=400.0, Ls=(20, 40, 80), weights=(4, 3, 2),
-                                                 sweeps=200, seed=4)
-    out = serve_load.replay(ctx, sites, arrivals, weiss, n_iter=3, sweeps=200, warm_first=40, warm_next=10, n_bins=4,
-                            timeout_s=120)
+def test_replay_small_stream(ctx, batch_ctx):
+    """Timed steps (the default mode): a short Poisson stream over four L
+    classes; the last iteration of every site is rechecked against a batch
+    solve that starts from the fields the site had before it."""
+    sites, arrivals, weiss = wl.serving_requests(n_sites=12, n_iter=3, rate=400.0, Ls=(20, 40, 80, 160),
+                                                 weights=(4, 3, 2, 1), sweeps=200, seed=4)
+    ctx.serve_config(step_ms=2.0)
+    try:
+        out = serve_load.replay(ctx, sites, arrivals, weiss, n_iter=3, sweeps=200, warm_first=40, warm_next=10,
+                                n_bins=4, timeout_s=120)
+    finally:
+        ctx.serve_config(quantum_proposals=900)
     assert out["requests"] == 36 and out["p99_ms"] >= out["p50_ms"] > 0
     assert out["proposals"] == sum(200 * s["L"] for s in sites) * 3
+    res = out["results"]
+    for i, s in enumerate(sites):
+        p = serve_load.site_request(s, 2, weiss, 200, 40, 10, n_bins=4)
+        p["init_fields"] = res[(i, 1)]["fields"]
+        p["delay"] = 0
+        _same(res[(i, 2)], batch_ctx.solve([p])[0])
