@@ -23,6 +23,26 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Compile-time case selection: f(std::integral_constant<int, idx>) for a
+// run-time idx in [0, N), by a binary tree of uniform branches (depth
+// log2 N instead of a chain of N compares); every leaf sees a constant.
+template <int Lo, int Hi, class F>
+__device__ __forceinline__ void dispatch_impl(int idx, F&& f) {
+  if constexpr (Hi - Lo == 1) {
+    f(std::integral_constant<int, Lo>{});
+  } else {
+    constexpr int Mid = (Lo + Hi) / 2;
+    if (idx < Mid)
+      dispatch_impl<Lo, Mid>(idx, f);
+    else
+      dispatch_impl<Mid, Hi>(idx, f);
+  }
+}
+template <int N, class F>
+__device__ __forceinline__ void dispatch(int idx, F&& f) {
+  dispatch_impl<0, N>(idx, f);
+}
+
 // ------------------------------------------------------------- Philox4x64-10
 // Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten
 // rounds of two 64x64->128 multiplies, Weyl key schedule.

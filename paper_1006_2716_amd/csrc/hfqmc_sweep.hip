@@ -144,22 +144,31 @@ struct Engine {
     const int tl = l >> 4, cl = l & 15, ql = (l & 15) >> 2, rl = l & 3;
     Stage<C>& mine = sm.u.w.stage[buf][spin];
     if (c == cl) {
-      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
-        if (tj == tl)
-          static_for<RT>([&](auto rt) __attribute__((always_inline)) {
-            static_for<4>([&](auto r) __attribute__((always_inline)) { mine.col[row_of(rt, r)] = gget(rt, tj, r); });
-          });
+      dispatch<NT>(tl, [&](auto tj) __attribute__((always_inline)) {
+        static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+          static_for<4>([&](auto r) __attribute__((always_inline)) { mine.col[row_of(rt, r)] = gget(rt, tj, r); });
+        });
+        __asm__ volatile("" ::: "memory");  // keeps the leaves' stores apart (no pointer phi)
       });
     }
     if (q == ql && tl / RT == wr) {
-      const int rtl = tl % RT;
-      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
-        if (rt == rtl)
-          static_for<4>([&](auto r) __attribute__((always_inline)) {
-            if (r == rl)
-              static_for<NT>([&](auto tj) __attribute__((always_inline)) { mine.row[tj * 16 + c] = gget(rt, tj, r); });
-          });
+      dispatch<RT * 4>((tl % RT) * 4 + rl, [&](auto k) __attribute__((always_inline)) {
+        constexpr int rt = decltype(k)::value / 4, r = decltype(k)::value % 4;
+        static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+          mine.row[tj * 16 + c] = gget(std::integral_constant<int, rt>{}, tj, std::integral_constant<int, r>{});
+        });
+        __asm__ volatile("" ::: "memory");
       });
+    }
+    if constexpr (C::DK == 0) {
+      // Rank-one kernels stage G[:,l] - e_l: the diagonal copies equal the
+      // tile diagonal bit for bit here, so lane l % 64 of the wave holding
+      // row l (the column's stager for that row is in the same wave, its
+      // store precedes this one) overwrites entry l with G[l][l] - 1.
+      if (tl / RT == wr && lane == (l & 63)) {
+        const int jj = l >> 6;
+        mine.col[l] = (spin == 0 ? pick<JW>(dgu, jj) : pick<JW>(dgd, jj)) - 1.0;
+      }
     }
   }
   __device__ __forceinline__ const double* colp(int s, int l) const { return sm.u.w.stage[buf][s].col; }
@@ -176,9 +185,10 @@ struct Engine {
     });
     static_for<RT>([&](auto rt) __attribute__((always_inline)) {
       static_for<4>([&](auto r) __attribute__((always_inline)) {
-        const int i = row_of(rt, r);
         double x = a[rt][r];
-        if (i == l) x -= 1.0;
+        if constexpr (C::DK != 0) {
+          if (row_of(rt, r) == l) x -= 1.0;
+        }
         a[rt][r] = f * x;
       });
     });
@@ -188,9 +198,11 @@ struct Engine {
       const int m = lane + 64 * jj;
       if (m < LT) {
         double xu = cu[m], xd = cd[m];
-        if (m == l) {
-          xu -= 1.0;
-          xd -= 1.0;
+        if constexpr (C::DK != 0) {
+          if (m == l) {
+            xu -= 1.0;
+            xd -= 1.0;
+          }
         }
         dgu[jj] = __builtin_fma(fu * xu, ru[m], dgu[jj]);
         dgd[jj] = __builtin_fma(fd * xd, rd[m], dgd[jj]);
@@ -302,15 +314,19 @@ struct Engine {
   __device__ __forceinline__ int scan(int l0, const double (&uv)[JW], double& fu, double& fd, int64_t& nonpos,
                                       int64_t& err) {
     uint64_t acc_mask[JW], bad_mask[JW];
-    double Ru[JW], Rd[JW];
+    double Fu[JW], Fd[JW];
     static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
       const bool live = m >= l0 && m < L;
-      Ru[jj] = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
-      Rd[jj] = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
-      const double R = Ru[jj] * Rd[jj];
+      const double Ru = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
+      const double Rd = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
+      const double R = Ru * Rd;
       acc_mask[jj] = __ballot(live && uv[jj] < R);
       bad_mask[jj] = __ballot(live && !(R > 0.0));
+      // every lane forms its own factors d_s / R_s, off the critical path of
+      // the ballot; the accepted lane's pair is read out below
+      Fu[jj] = fpu[jj] * recip(Ru);
+      Fd[jj] = fpd[jj] * recip(Rd);
     });
     int l = L;
     static_for<JW>([&](auto k) __attribute__((always_inline)) {
@@ -325,9 +341,8 @@ struct Engine {
       if (bad) err = 1;  // R <= 0 or NaN: impossible in exact arithmetic
     });
     const int ls = l < L ? l : 0, jj = ls >> 6, ln = ls & 63;
-    const double ru = readlane_d(pick<JW>(Ru, jj), ln), rd = readlane_d(pick<JW>(Rd, jj), ln);
-    fu = readlane_d(pick<JW>(fpu, jj), ln) * recip(ru);
-    fd = readlane_d(pick<JW>(fpd, jj), ln) * recip(rd);
+    fu = readlane_d(pick<JW>(Fu, jj), ln);
+    fd = readlane_d(pick<JW>(Fd, jj), ln);
     return l;
   }
 
