@@ -47,8 +47,8 @@ RECOMPUTE_EVERY = 50
 # HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
 # FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
 # valid only for the kernel source with this sha256 prefix.
-PROFILED_KERNEL_SHA = "c61e9927319b6a81"
-PROFILED_TRAFFIC_BYTES = 1.627e9
+PROFILED_KERNEL_SHA = "485566452dcee507"
+PROFILED_TRAFFIC_BYTES = 1.897e9
 
 
 def kernel_sha() -> str:
@@ -177,6 +177,8 @@ def bench_uneven(args):
            "tune_seconds": round(tune_s, 2), "plan_rt_k_by_L": {str(L): v for L, v in plans.items()},
            "class_launch_ms_L_items": launches},
           p99_solve_ms=float(np.percentile(step_ms, 99)), mixed_delayed=mixed)
+    mctx.close()
+    ctx.close()
 
 
 def bench_serving(args):

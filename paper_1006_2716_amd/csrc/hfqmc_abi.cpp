@@ -603,7 +603,16 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws,
       return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", i, plan[i].dk ? "delayed-update" : "sweep",
                   p[i].L);
   }
-  auto cost = [&](int i) { return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * p[i].L; };
+  // expected work: sweeps x L proposals, a fraction exp(-0.76 lambda^2) of
+  // them accepted (fits the measured acceptance of the chain workloads at
+  // both ends of U in [4, 12]), each accept about max(L, 64) units.  The
+  // heaviest items start first; when all items are resident at once this
+  // also places the heaviest beside the lightest (measured: 97 -> 85 ms on
+  // the 512 x L = 64 batch with U in [4, 12])
+  auto cost = [&](int i) {
+    const double lam = coupling(p[i].beta / p[i].L, p[i].U);
+    return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * std::max(p[i].L, 64) * std::exp(-0.76 * lam * lam);
+  };
   auto key = [&](int i) { return std::make_tuple(-padded_L(p[i].L), plan[i].dk, plan[i].rt); };
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
     if (key(a) != key(b)) return key(a) < key(b);

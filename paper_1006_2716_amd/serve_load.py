@@ -34,6 +34,8 @@ def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, wa
     due = list(np.asarray(arrivals, dtype=float))
     arrive = [None] * n        # arrival time of the site's current request
     ticket = [None] * n
+    step0 = [0] * n            # engine step count when the request was queued
+    steps_per_request = []
     lat, lat_L, results = [], {}, {}
     proposals = 0
     t0 = time.perf_counter()
@@ -52,6 +54,7 @@ def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, wa
                                                             n_bins))
                     if t is not None:
                         ticket[i] = t
+                        step0[i] = ctx.serve_stats()["steps"]
             for i in range(n):
                 if ticket[i] is None:
                     continue
@@ -59,6 +62,7 @@ def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, wa
                 if r is None:
                     continue
                 done = time.perf_counter() - t0
+                steps_per_request.append(ctx.serve_stats()["steps"] - step0[i])
                 ms = (done - arrive[i]) * 1e3
                 lat.append(ms)
                 lat_L.setdefault(sites[i]["L"], []).append(ms)
@@ -92,4 +96,5 @@ def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, wa
                 max_ms=float(lat.max()), requests=int(lat.size), makespan_s=makespan,
                 proposals=int(proposals), proposals_per_s=proposals / makespan,
                 p50_ms_by_L={int(k): float(np.median(v)) for k, v in sorted(lat_L.items())},
+                steps_per_request_p50=float(np.median(steps_per_request)),
                 results=results)
