@@ -92,10 +92,12 @@ struct Engine {
   __device__ __forceinline__ Engine(Smem<C>& s)
       : sm(s),
         tid(threadIdx.x),
-        wave(threadIdx.x >> 6),
+        // wave-level values through readfirstlane: the compiler then knows
+        // they are uniform and keeps every branch and select on them scalar
+        wave(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)),
         lane(threadIdx.x & 63),
-        spin((threadIdx.x >> 6) / WPS),
-        wr((threadIdx.x >> 6) % WPS),
+        spin(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) / WPS),
+        wr(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % WPS),
         q((threadIdx.x & 63) >> 4),
         c(threadIdx.x & 15),
         buf(0) {}

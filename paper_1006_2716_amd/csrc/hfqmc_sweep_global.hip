@@ -61,7 +61,7 @@ struct EngineG {
   double* gm = nullptr;     // G_up, G_dn (LT x LT each), then the drift snapshot of both
 
   __device__ __forceinline__ EngineG(GSmem<C>& s)
-      : sm(s), tid(threadIdx.x), wave(threadIdx.x >> 6), lane(threadIdx.x & 63) {}
+      : sm(s), tid(threadIdx.x), wave(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)), lane(threadIdx.x & 63) {}
 
   __device__ __forceinline__ void set_field(int jj, int s) {
     sv[jj] = s;
