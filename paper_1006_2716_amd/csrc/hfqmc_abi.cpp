@@ -95,10 +95,12 @@ int default_rt(int LT, int dk) {
   return 1;
 }
 
-// Bytes of G state per impurity: both spins plus the drift snapshot.
+// Bytes of state per impurity: G of both spins, then a second 2 L^2 region
+// (the drift snapshot of the device-memory kernel, the parked bin sums of G
+// of the register kernels), then 3 x 64 parked per-lane sums.
 size_t state_bytes(int L) {
   const size_t LT = (size_t)((L + 15) / 16 * 16);
-  return sizeof(double) * 4 * LT * LT;
+  return sizeof(double) * (4 * LT * LT + 256);
 }
 
 // HS coupling from cosh(lambda) = exp(dtau U / 2), written as
@@ -1066,7 +1068,8 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     c->tune_all = read_tune_cache(c->tune_path);
     for (const auto& t : c->tune_all) {
       const int dk = t.rt == 0 ? 1 : (t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0);
-      if (t.prec == prec_name(precision) && t.k >= 1 && t.k <= kMaxDelay && find_kernel(t.LT, t.rt, dk))
+      const int kmax = t.rt == 0 ? kGlobalMaxDelay : kMaxDelay;
+      if (t.prec == prec_name(precision) && t.k >= 1 && t.k <= kmax && find_kernel(t.LT, t.rt, dk))
         c->tune[t.LT] = t;
     }
   }

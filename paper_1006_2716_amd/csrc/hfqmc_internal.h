@@ -56,8 +56,9 @@ struct alignas(16) ImpDesc {
   int64_t off_fields;       // L int8 fields (in and out)
   int64_t off_bins;         // n_bins x NV doubles: per-bin sums (accumulated)
   int64_t off_status;       // ImpStatus
-  int64_t off_state;        // 4 x LT x LT doubles: G of both spins (register kernels: tiles in
-                            // lane order; global kernel: row-major), then a drift snapshot
+  int64_t off_state;        // 4 x LT x LT + 256 doubles: G of both spins (register kernels:
+                            // tiles in lane order; global kernel: row-major), then the drift
+                            // snapshot (global kernel) or parked bin sums (register kernels)
   int64_t off_force;        // OP_FORCE: n_force int32 slices, then n_force doubles ratios
   int64_t off_init;         // F_FIELDS_GIVEN: L int8 initial fields (read only)
   int64_t pad_;

@@ -43,6 +43,9 @@ struct Cfg {
   static constexpr int GS = LT + 1;       // padded LDS row stride of a dumped matrix
   static constexpr int MINB = LT <= 64 ? 2 : 1;  // workgroups per CU the register budget targets
   static constexpr bool DUMP2 = LT <= 64;        // both spins fit the LDS dump area at once
+  // rank-one kernels up to 64 slices sum G over a bin's sweeps in LDS and
+  // evaluate the g(tau) estimator once per bin (it is linear in G)
+  static constexpr bool ACC = DK == 0 && LT <= 64;
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
   static_assert(NTH >= 2 * LT, "measurement needs one thread per (spin, tau_k)");
 };
@@ -62,8 +65,9 @@ struct Smem {
   };
   union {
     Work w;
-    double dump[(C::DUMP2 ? 2 : 1) * C::LT * C::GS];  // G for the g(tau) estimator
+    double dump[C::ACC ? 2 * C::LT : (C::DUMP2 ? 2 : 1) * C::LT * C::GS];  // G for the g(tau) estimator
   } u;
+  double gsum[C::ACC ? 2 * C::LT * C::GS : 1];  // running bin sum of G_up, G_dn (row stride GS)
   double weiss[2][C::LT];  // Weiss samples, zero padded
   double red[C::NW];
   int item;
@@ -371,6 +375,20 @@ struct Engine {
     return reinterpret_cast<double*>(ws + d.off_state) + (size_t)tid * (RT * NT * 4);
   }
 
+  // Running bin sums parked in the state area between launches (rank-one
+  // kernels up to 64 slices): G sums after the tiles and their snapshot
+  // region, lane-contiguous like the tiles; then 3 x 64 per-lane sums.
+  __device__ __forceinline__ double* gsum_state(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + 2 * (size_t)LT * LT + (size_t)tid * (RT * NT * 4);
+  }
+  __device__ __forceinline__ double* lsum_state(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + 4 * (size_t)LT * LT;
+  }
+  // This lane's elements of the LDS running sum of its spin's G.
+  __device__ __forceinline__ double* gsum_ptr() const {
+    return sm.gsum + spin * (LT * GS) + row_of(0, 0) * GS + c;
+  }
+
   __device__ __forceinline__ void save_tiles(uint8_t* ws) {
     double* p = state_ptr(ws);
     for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
@@ -390,25 +408,14 @@ struct Engine {
   // (uniform) when `drift` is set; G_old is parked in the state area.
   __device__ __forceinline__ double recompute(uint8_t* ws, bool drift) {
     if (drift) save_tiles(ws);
-    // G = G0: each spin's antiperiodic matrix is written to the dump area and
-    // the waves of that spin load their elements from there.
-    static_for<2>([&](auto s) __attribute__((always_inline)) {
-      __syncthreads();
-      for (int idx = tid; idx < LT * LT; idx += C::NTH) {
-        const int i = idx / LT, j = idx % LT;
-        double v = 0.0;
-        if (i < L && j < L) v = i >= j ? sm.weiss[s][i - j] : -sm.weiss[s][i - j + L];
-        sm.u.dump[i * GS + j] = v;
-      }
-      __syncthreads();
-      if (spin == s) {
-        const double* src = sm.u.dump + row_of(0, 0) * GS + c;
-        for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
-          gset(rt, tj, r, src[(rt * 16 + r) * GS + tj * 16]);
-        });
-      }
+    // G = G0, the antiperiodic matrix of this wave's spin, element by element
+    // from the Weiss samples in LDS
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      const int i = row_of(rt, r), j = tj * 16 + c;
+      double v = 0.0;
+      if (i < L && j < L) v = i >= j ? sm.weiss[spin][i - j] : -sm.weiss[spin][i - j + L];
+      gset(rt, tj, r, v);
     });
-    __syncthreads();
     {
       const double g0u = sm.weiss[0][0], g0d = sm.weiss[1][0];
       static_for<JW>([&](auto jj) __attribute__((always_inline)) {
@@ -550,6 +557,30 @@ struct Engine {
       double nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
       int64_t cur_bin = -1;
       const int64_t nm = d.n_measure, nb = d.n_bins;
+      // ACC kernels: lane sums over the bin's sweeps of 1 - G_up[m][m],
+      // 1 - G_dn[m][m] and their product (slice m = lane), and the LDS sum
+      // of G; a bin that a previous launch left open continues from the
+      // sums it parked, so a split chain adds in the order of one launch
+      double su = 0.0, sd = 0.0, sx = 0.0;
+      if constexpr (C::ACC) {
+        const int64_t m0 = d.sweep_begin - d.n_warmup;
+        const bool cont = (flags & F_RESUME) && m0 > 0 && m0 < nm && (m0 * nb) / nm == ((m0 - 1) * nb) / nm;
+        double* gp = gsum_ptr();
+        if (cont) {
+          const double* src = gsum_state(ws);
+          for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+            gp[(rt * 16 + r) * GS + tj * 16] = src[(rt * NT + tj) * 4 + r];
+          });
+          const double* la = lsum_state(ws);
+          su = la[lane];
+          sd = la[64 + lane];
+          sx = la[128 + lane];
+        } else {
+          for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+            gp[(rt * 16 + r) * GS + tj * 16] = 0.0;
+          });
+        }
+      }
       int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
         double uv[JW];
@@ -594,7 +625,43 @@ struct Engine {
           max_drift = fmax(max_drift, recompute(ws, true));
           next_rec += d.recompute_every;
         }
-        if (w >= d.n_warmup) {
+        if (C::ACC && w >= d.n_warmup) {
+          const int64_t m = w - d.n_warmup;
+          const int64_t b = (m * nb) / nm;
+          double* gp = gsum_ptr();
+          for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+            gp[(rt * 16 + r) * GS + tj * 16] += gget(rt, tj, r);
+          });
+          if (lane < L) {
+            su += 1.0 - dgu[0];
+            sd += 1.0 - dgd[0];
+            sx += (1.0 - dgu[0]) * (1.0 - dgd[0]);
+          }
+          if ((m + 1 == nm) || (((m + 1) * nb) / nm != b)) {  // the bin is complete: evaluate it
+            __syncthreads();
+            double* bp = bins + (size_t)b * NV;
+            if (tid < 2 * L) {
+              const int sp = tid >= L, k = tid - sp * L;
+              bp[tid + (tid >= L)] = diag_sum(sm.gsum + sp * (LT * GS), k) / (double)L;
+            }
+            if (wave == 0) {
+              const double nu = wave_sum(su) / (double)L, nd = wave_sum(sd) / (double)L;
+              const double dx = wave_sum(sx) / (double)L;
+              if (lane == 0) {
+                bp[L] = nu;
+                bp[2 * L + 1] = nd;
+                bp[2 * L + 2] = nu;
+                bp[2 * L + 3] = nd;
+                bp[2 * L + 4] = dx;
+              }
+            }
+            __syncthreads();
+            for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+              gp[(rt * 16 + r) * GS + tj * 16] = 0.0;
+            });
+            su = sd = sx = 0.0;
+          }
+        } else if (w >= d.n_warmup) {
           const int64_t m = w - d.n_warmup;
           const int64_t b = (m * nb) / nm;
           double* bp = bins + (size_t)b * NV;
@@ -618,7 +685,7 @@ struct Engine {
           nacc_u += wave_sum(xu) / (double)L;
           nacc_d += wave_sum(xd) / (double)L;
           dacc += wave_sum(xx) / (double)L;
-          measure_green(gacc);
+          if constexpr (!C::ACC) measure_green(gacc);
           const bool last = (m + 1 == nm) || (((m + 1) * nb) / nm != b) || (w + 1 == d.sweep_end);
           if (last) {
             if (tid < 2 * L) bp[tid + (tid >= L)] = gacc;
@@ -630,6 +697,23 @@ struct Engine {
               bp[2 * L + 4] = dacc;
             }
             cur_bin = -1;
+          }
+        }
+      }
+      if constexpr (C::ACC) {
+        // a bin still open when this launch ends: park its running sums
+        const int64_t ml = d.sweep_end - 1 - d.n_warmup;
+        if (d.sweep_end > d.sweep_begin && ml >= 0 && ml + 1 < nm && ((ml + 1) * nb) / nm == (ml * nb) / nm) {
+          const double* gp = gsum_ptr();
+          double* dst = gsum_state(ws);
+          for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+            dst[(rt * NT + tj) * 4 + r] = gp[(rt * 16 + r) * GS + tj * 16];
+          });
+          if (wave == 0) {
+            double* la = lsum_state(ws);
+            la[lane] = su;
+            la[64 + lane] = sd;
+            la[128 + lane] = sx;
           }
         }
       }

@@ -133,3 +133,38 @@ def test_autotuner_picks_measured_shape_and_persists(tmp_path):
     finally:
         c.close()
         torch.cuda.synchronize()
+
+
+def test_tune_cache_ignores_foreign_or_broken_entries(tmp_path):
+    """A cache for another architecture, a malformed file, or entries naming
+    shapes this build does not have leave the untuned defaults in place."""
+    from paper_1006_2716_amd import hfqmc
+    ref = hfqmc.Context(0)
+    defaults = {L: ref.plan(L, 0) for L in (32, 64, 128, 160)}
+    ref.close()
+    cases = {
+        "other_arch.json": '{"arch": "gfx942", "entries": [{"precision": "fp64", "L_padded": 64, "rt": 4, "k": 1}]}',
+        "broken.json": '{"arch": "gfx950", "entries": [{"precision": "fp64", "L_padded": 64, "rt": ',
+        "bad_shape.json": '{"arch": "gfx950", "entries": [{"precision": "fp64", "L_padded": 64, "rt": 3, "k": 1},'
+                          ' {"precision": "fp64", "L_padded": 160, "rt": 0, "k": 64}]}',
+        "other_precision.json": '{"arch": "gfx950", "entries": [{"precision": "mixed", "L_padded": 64, "rt": 4, "k": 1}]}',
+    }
+    for name, text in cases.items():
+        path = tmp_path / name
+        path.write_text(text)
+        c = hfqmc.Context(0, tune_cache=str(path))
+        try:
+            for L, plan in defaults.items():
+                assert c.plan(L, 0) == plan, (name, L)
+        finally:
+            c.close()
+    # a valid entry is honoured
+    path = tmp_path / "good.json"
+    path.write_text('{"arch": "gfx950", "entries": [{"precision": "fp64", "L_padded": 64, "rt": 4, "k": 1, '
+                    '"proposals_per_s": 1.0}]}')
+    c = hfqmc.Context(0, tune_cache=str(path))
+    try:
+        assert c.plan(64, 0)[:2] == (4, 1) and c.plan(64, 1)[:2] == (4, 1)
+        assert c.plan(64, 8)[:2] == (2, 8)  # an explicit delay keeps its own shape
+    finally:
+        c.close()
