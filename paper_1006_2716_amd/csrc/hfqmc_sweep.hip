@@ -43,9 +43,10 @@ struct Cfg {
   static constexpr int GS = LT + 1;       // padded LDS row stride of a dumped matrix
   static constexpr int MINB = LT <= 64 ? 2 : 1;  // workgroups per CU the register budget targets
   static constexpr bool DUMP2 = LT <= 64;        // both spins fit the LDS dump area at once
-  // rank-one kernels up to 64 slices sum G over a bin's sweeps in LDS and
-  // evaluate the g(tau) estimator once per bin (it is linear in G)
-  static constexpr bool ACC = DK == 0 && LT <= 64;
+  // rank-one kernels up to 96 slices sum G over a bin's sweeps in LDS and
+  // evaluate the g(tau) estimator once per bin (it is linear in G); the sum
+  // of both spins takes 2 LT (LT + 1) doubles (149 KiB at LT = 96)
+  static constexpr bool ACC = DK == 0 && LT <= 96;
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
   static_assert(NTH >= 2 * LT, "measurement needs one thread per (spin, tau_k)");
 };
@@ -558,7 +559,7 @@ struct Engine {
       int64_t cur_bin = -1;
       const int64_t nm = d.n_measure, nb = d.n_bins;
       // ACC kernels: lane sums over the bin's sweeps of 1 - G_up[m][m],
-      // 1 - G_dn[m][m] and their product (slice m = lane), and the LDS sum
+      // 1 - G_dn[m][m] and their product (slices m = lane + 64 jj), and the LDS sum
       // of G; a bin that a previous launch left open continues from the
       // sums it parked, so a split chain adds in the order of one launch
       double su = 0.0, sd = 0.0, sx = 0.0;
@@ -632,11 +633,13 @@ struct Engine {
           for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
             gp[(rt * 16 + r) * GS + tj * 16] += gget(rt, tj, r);
           });
-          if (lane < L) {
-            su += 1.0 - dgu[0];
-            sd += 1.0 - dgd[0];
-            sx += (1.0 - dgu[0]) * (1.0 - dgd[0]);
-          }
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+            if (lane + 64 * jj < L) {
+              su += 1.0 - dgu[jj];
+              sd += 1.0 - dgd[jj];
+              sx += (1.0 - dgu[jj]) * (1.0 - dgd[jj]);
+            }
+          });
           if ((m + 1 == nm) || (((m + 1) * nb) / nm != b)) {  // the bin is complete: evaluate it
             __syncthreads();
             double* bp = bins + (size_t)b * NV;
