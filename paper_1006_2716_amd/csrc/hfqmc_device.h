@@ -116,6 +116,71 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Per-wave copy of an impurity's slice state: slice m lives in lane m % 64,
+// word m / 64.  Every wave of the workgroup keeps its own copy and takes the
+// same Metropolis decisions from it, so rejections need no communication.
+template <int JW>
+struct SliceState {
+  double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn
+  double fpu[JW], fpd[JW];  // flip factors exp(-2 sigma lambda s_m) - 1 of the slices
+  int sv[JW];               // fields s_m
+
+  __device__ __forceinline__ void set_field(int jj, int s, double dflip_p, double dflip_m) {
+    sv[jj] = s;
+    fpu[jj] = s > 0 ? dflip_p : dflip_m;  // up:   exp(-2 lambda s) - 1
+    fpd[jj] = s > 0 ? dflip_m : dflip_p;  // down: exp(+2 lambda s) - 1
+  }
+
+  __device__ __forceinline__ void flip_field(int l, int lane, double dflip_p, double dflip_m) {
+    const int jj = l >> 6, ln = l & 63;
+    if (lane == ln)
+      static_for<JW>([&](auto k) __attribute__((always_inline)) {
+        if (k == jj) set_field(k, -sv[k], dflip_p, dflip_m);
+      });
+  }
+
+  // Vectorised Metropolis scan over slices [l0, L): rejections leave G
+  // unchanged, so every remaining slice is tested against the current
+  // diagonals at once (lane m tests slice m with exactly the arithmetic of a
+  // sequential scan) and the first accepted slice is found by a wave ballot.
+  // Returns that slice (L if none) and its factors f_s = d_s / R_s; counts
+  // the rejected R <= 0 (never seen in exact arithmetic) into nonpos/err.
+  __device__ __forceinline__ int scan(int l0, int L, int lane, const double (&uv)[JW], double& fu, double& fd,
+                                      int64_t& nonpos, int64_t& err) const {
+    uint64_t acc_mask[JW], bad_mask[JW];
+    double Fu[JW], Fd[JW];
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      const int m = lane + 64 * jj;
+      const bool live = m >= l0 && m < L;
+      const double Ru = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
+      const double Rd = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
+      const double R = Ru * Rd;
+      acc_mask[jj] = __ballot(live && uv[jj] < R);
+      bad_mask[jj] = __ballot(live && !(R > 0.0));
+      // every lane forms its own factors d_s / R_s, off the critical path of
+      // the ballot; the accepted lane's pair is read out below
+      Fu[jj] = fpu[jj] * recip(Ru);
+      Fd[jj] = fpd[jj] * recip(Rd);
+    });
+    int l = L;
+    static_for<JW>([&](auto k) __attribute__((always_inline)) {
+      constexpr int jj = JW - 1 - decltype(k)::value;  // highest word first, lowest wins
+      if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
+    });
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      const int hi = l - 64 * jj;  // slices below l were rejected
+      const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
+      const uint64_t bad = bad_mask[jj] & below;
+      nonpos += __builtin_popcountll(bad);
+      if (bad) err = 1;
+    });
+    const int ls = l < L ? l : 0, jj = ls >> 6, ln = ls & 63;
+    fu = readlane_d(pick<JW>(Fu, jj), ln);
+    fd = readlane_d(pick<JW>(Fd, jj), ln);
+    return l;
+  }
+};
+
 // One compiled sweep kernel.  RT = tile-rows per wave of the register-tile
 // kernels, 0 for the global-memory kernel; DK = update kind (0 rank-one,
 // 1 delayed fp64, 2 delayed with fp32 products).

@@ -76,16 +76,19 @@ struct Smem {
 
 // ------------------------------------------------------------- the engine
 template <class C>
-struct Engine {
+struct Engine : SliceState<C::JW> {
   static constexpr int LT = C::LT, RT = C::RT, NT = C::NT, WPS = C::WPS, JW = C::JW, GS = C::GS;
+  using Slices = SliceState<C::JW>;
+  using Slices::dgu;
+  using Slices::dgd;
+  using Slices::fpu;
+  using Slices::fpd;
+  using Slices::sv;
 
   Smem<C>& sm;
   const int tid, wave, lane, spin, wr, q, c;
   // register state
   double g[RT][NT][4];      // this wave's tiles of G_spin
-  double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn for slices lane + 64 jj
-  double fpu[JW], fpd[JW];  // flip factors exp(-2 s lambda s_m) - 1 of those slices
-  int sv[JW];               // fields of those slices
   int buf;                  // staging double-buffer selector (uniform)
   int kb = 0;               // delayed updates pending in the panels (uniform)
   int kdepth = 1;           // flush when kb reaches this depth
@@ -127,19 +130,8 @@ struct Engine {
     g[decltype(rt)::value][decltype(tj)::value][decltype(r)::value] = x;
   }
 
-  __device__ __forceinline__ void set_field(int jj, int s) {
-    sv[jj] = s;
-    fpu[jj] = s > 0 ? d.dflip_p : d.dflip_m;  // up:   exp(-2 lambda s) - 1
-    fpd[jj] = s > 0 ? d.dflip_m : d.dflip_p;  // down: exp(+2 lambda s) - 1
-  }
-
-  __device__ __forceinline__ void flip_field(int l) {
-    const int jj = l >> 6, ln = l & 63;
-    if (lane == ln)
-      static_for<JW>([&](auto k) __attribute__((always_inline)) {
-        if (k == jj) set_field(k, -sv[k]);
-      });
-  }
+  __device__ __forceinline__ void set_field(int jj, int s) { Slices::set_field(jj, s, d.dflip_p, d.dflip_m); }
+  __device__ __forceinline__ void flip_field(int l) { Slices::flip_field(l, lane, d.dflip_p, d.dflip_m); }
 
   // Owners write column l and row l of their spin's G to the staging buffer.
   // Column l lives in tile-column l/16 of the lanes with c == l%16; row l in
@@ -313,44 +305,9 @@ struct Engine {
     }
   }
 
-  // Vectorised Metropolis scan over slices [l0, L): rejections leave G
-  // unchanged, so every remaining slice is tested against the current
-  // diagonals at once (lane m tests slice m with exactly the arithmetic of a
-  // sequential scan) and the first accepted slice is found by a wave ballot.
-  // Returns that slice (L if none) and its factors f_s = d_s / R_s.
   __device__ __forceinline__ int scan(int l0, const double (&uv)[JW], double& fu, double& fd, int64_t& nonpos,
-                                      int64_t& err) {
-    uint64_t acc_mask[JW], bad_mask[JW];
-    double Fu[JW], Fd[JW];
-    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-      const int m = lane + 64 * jj;
-      const bool live = m >= l0 && m < L;
-      const double Ru = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
-      const double Rd = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
-      const double R = Ru * Rd;
-      acc_mask[jj] = __ballot(live && uv[jj] < R);
-      bad_mask[jj] = __ballot(live && !(R > 0.0));
-      // every lane forms its own factors d_s / R_s, off the critical path of
-      // the ballot; the accepted lane's pair is read out below
-      Fu[jj] = fpu[jj] * recip(Ru);
-      Fd[jj] = fpd[jj] * recip(Rd);
-    });
-    int l = L;
-    static_for<JW>([&](auto k) __attribute__((always_inline)) {
-      constexpr int jj = JW - 1 - decltype(k)::value;  // highest word first, lowest wins
-      if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
-    });
-    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-      const int hi = l - 64 * jj;  // slices below l were rejected
-      const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
-      const uint64_t bad = bad_mask[jj] & below;
-      nonpos += __builtin_popcountll(bad);
-      if (bad) err = 1;  // R <= 0 or NaN: impossible in exact arithmetic
-    });
-    const int ls = l < L ? l : 0, jj = ls >> 6, ln = ls & 63;
-    fu = readlane_d(pick<JW>(Fu, jj), ln);
-    fd = readlane_d(pick<JW>(Fd, jj), ln);
-    return l;
+                                      int64_t& err) const {
+    return Slices::scan(l0, L, lane, uv, fu, fd, nonpos, err);
   }
 
   // Rebuild the diagonal copies from the tiles (after loading saved state).

@@ -45,15 +45,18 @@ struct GSmem {
 };
 
 template <class C>
-struct EngineG {
+struct EngineG : SliceState<C::JW> {
   static constexpr int LT = C::LT, NT = C::NT, JW = C::JW, KP = C::KP;
   typedef double d4 __attribute__((ext_vector_type(4)));
+  using Slices = SliceState<C::JW>;
+  using Slices::dgu;
+  using Slices::dgd;
+  using Slices::fpu;
+  using Slices::fpd;
+  using Slices::sv;
 
   GSmem<C>& sm;
   const int tid, wave, lane;
-  double dgu[JW], dgd[JW];  // diagonals of G_up, G_dn for slices lane + 64 jj
-  double fpu[JW], fpd[JW];  // flip factors of those slices
-  int sv[JW];               // fields of those slices
   int kb = 0;               // pending delayed updates (uniform)
   int kdepth = KP;          // flush depth
   int L = 0;
@@ -63,19 +66,8 @@ struct EngineG {
   __device__ __forceinline__ EngineG(GSmem<C>& s)
       : sm(s), tid(threadIdx.x), wave(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)), lane(threadIdx.x & 63) {}
 
-  __device__ __forceinline__ void set_field(int jj, int s) {
-    sv[jj] = s;
-    fpu[jj] = s > 0 ? d.dflip_p : d.dflip_m;  // up:   exp(-2 lambda s) - 1
-    fpd[jj] = s > 0 ? d.dflip_m : d.dflip_p;  // down: exp(+2 lambda s) - 1
-  }
-
-  __device__ __forceinline__ void flip_field(int l) {
-    const int jj = l >> 6, ln = l & 63;
-    if (lane == ln)
-      static_for<JW>([&](auto k) __attribute__((always_inline)) {
-        if (k == jj) set_field(k, -sv[k]);
-      });
-  }
+  __device__ __forceinline__ void set_field(int jj, int s) { Slices::set_field(jj, s, d.dflip_p, d.dflip_m); }
+  __device__ __forceinline__ void flip_field(int l) { Slices::flip_field(l, lane, d.dflip_p, d.dflip_m); }
 
   // Stores of every wave to G visible to the loads of every wave.
   __device__ __forceinline__ void publish() {
@@ -83,38 +75,9 @@ struct EngineG {
     __syncthreads();
   }
 
-  // Metropolis scan over slices [l0, L) against the current diagonals (all
-  // tests at once, first acceptance by ballot); see the register kernel.
   __device__ __forceinline__ int scan(int l0, const double (&uv)[JW], double& fu, double& fd, int64_t& nonpos,
-                                      int64_t& err) {
-    uint64_t acc_mask[JW], bad_mask[JW];
-    double Ru[JW], Rd[JW];
-    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-      const int m = lane + 64 * jj;
-      const bool live = m >= l0 && m < L;
-      Ru[jj] = __builtin_fma(1.0 - dgu[jj], fpu[jj], 1.0);
-      Rd[jj] = __builtin_fma(1.0 - dgd[jj], fpd[jj], 1.0);
-      const double R = Ru[jj] * Rd[jj];
-      acc_mask[jj] = __ballot(live && uv[jj] < R);
-      bad_mask[jj] = __ballot(live && !(R > 0.0));
-    });
-    int l = L;
-    static_for<JW>([&](auto k) __attribute__((always_inline)) {
-      constexpr int jj = JW - 1 - decltype(k)::value;
-      if (acc_mask[jj]) l = 64 * jj + __builtin_ctzll(acc_mask[jj]);
-    });
-    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
-      const int hi = l - 64 * jj;
-      const uint64_t below = hi >= 64 ? ~0ull : (hi <= 0 ? 0ull : ((1ull << hi) - 1));
-      const uint64_t bad = bad_mask[jj] & below;
-      nonpos += __builtin_popcountll(bad);
-      if (bad) err = 1;
-    });
-    const int ls = l < L ? l : 0, jj = ls >> 6, ln = ls & 63;
-    const double ru = readlane_d(pick<JW>(Ru, jj), ln), rd = readlane_d(pick<JW>(Rd, jj), ln);
-    fu = readlane_d(pick<JW>(fpu, jj), ln) * recip(ru);
-    fd = readlane_d(pick<JW>(fpd, jj), ln) * recip(rd);
-    return l;
+                                      int64_t& err) const {
+    return Slices::scan(l0, L, lane, uv, fu, fd, nonpos, err);
   }
 
   // Append the update of slice l with factors f_s = d_s / R_s: column and row
@@ -180,7 +143,9 @@ struct EngineG {
     if (wave < NTILE) load(wave, cur);
     for (int t0 = wave; t0 < NTILE; t0 += STEP) {
       if (t0 + STEP < NTILE) load(t0 + STEP, nxt);
-      for (int k0 = 0; k0 < kb; k0 += 4) {
+#pragma unroll
+      for (int k0 = 0; k0 < KP; k0 += 4) {  // unrolled over the panel capacity: fragment reads issue together
+        if (k0 >= kb) break;
         const int k = k0 + q;
         static_for<U>([&](auto u) __attribute__((always_inline)) {
           const int t = t0 + u * C::NW;
