@@ -44,7 +44,7 @@ class _Problem(C.Structure):
         ("n_warmup", C.c_int64), ("n_measure", C.c_int64),
         ("recompute_every", C.c_int32), ("n_bins", C.c_int32),
         ("seed", C.c_uint64), ("site", C.c_uint64), ("sweep_offset", C.c_int64),
-        ("init_fields", C.POINTER(C.c_int8)),
+        ("init_fields", C.POINTER(C.c_int8)), ("chain", C.c_uint64),
     ]
 
 
@@ -144,7 +144,8 @@ def run(problems, n_threads: int = 1, want_green: bool = False, want_hist: bool 
     """Run one Markov chain per problem dict.
 
     Problem keys: L, beta, U, weiss (2 x L array), n_warmup, n_measure,
-    recompute_every, n_bins, seed, site, [sweep_offset], [init_fields].
+    recompute_every, n_bins, seed, site, [sweep_offset], [init_fields],
+    [chain] (Philox counter word 3; independent chains of one impurity).
     Returns a list of dicts with 'bins' (n_bins x NV), 'fields', 'green',
     'proposals', 'accepts', 'nonpositive', 'max_drift', 'status'.
     """
@@ -168,7 +169,8 @@ def run(problems, n_threads: int = 1, want_green: bool = False, want_hist: bool 
                         int(p["n_warmup"]), int(p["n_measure"]), int(p.get("recompute_every", 50)),
                         int(p["n_bins"]), int(p["seed"]), int(p.get("site", i)),
                         int(p.get("sweep_offset", 0)),
-                        None if init_arr is None else init_arr.ctypes.data_as(C.POINTER(C.c_int8)))
+                        None if init_arr is None else init_arr.ctypes.data_as(C.POINTER(C.c_int8)),
+                        int(p.get("chain", 0)))
         R[i].bins = _dp(bins)
         R[i].final_fields = fields.ctypes.data_as(C.POINTER(C.c_int8))
         R[i].final_green = _dp(green) if green is not None else None
@@ -194,3 +196,26 @@ def summarize(bins: np.ndarray, L: int):
         g_up_err=err[0:L + 1], g_dn_err=err[L + 1:2 * L + 2],
         n_up=mean[2 * L + 2], n_dn=mean[2 * L + 3], docc=mean[2 * L + 4],
         n_up_err=err[2 * L + 2], n_dn_err=err[2 * L + 3], docc_err=err[2 * L + 4])
+
+
+def run_chains(problem, n_chains: int, n_threads: int = 1):
+    """Several independent chains of one impurity: chain j draws with
+    counter word 3 = j, runs the full warm-up and n_measure // n_chains
+    measured sweeps (the first n_measure % n_chains chains one more), and the
+    bins of the chains are pooled: bin b of the result is the mean over all
+    chains' measurements that fall in their bin b.  Returns the pooled bin
+    means, the per-bin measurement counts and the per-chain results."""
+    nm = int(problem["n_measure"])
+    nb = int(problem["n_bins"])
+    parts = [dict(problem, chain=j, n_measure=nm // n_chains + (1 if j < nm % n_chains else 0))
+             for j in range(n_chains)]
+    res = run(parts, n_threads=n_threads)
+    NV = res[0]["bins"].shape[1]
+    sums = np.zeros((nb, NV))
+    counts = np.zeros(nb)
+    for part, r in zip(parts, res):
+        m = np.arange(part["n_measure"])
+        cnt = np.bincount((m * nb) // part["n_measure"], minlength=nb).astype(float)
+        sums += r["bins"] * cnt[:, None]
+        counts += cnt
+    return sums / counts[:, None], counts, res

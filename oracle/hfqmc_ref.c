@@ -30,9 +30,11 @@
  *   G0 matrix: G0[i][j] = g(tau_{i-j}) for i >= j, -g(tau_{i-j+L}) for i < j.
  *   Sweep: slices l = 0..L-1 in order.  Random numbers: Philox4x64-10
  *   (Salmon, Moraes, Dror, Shaw, SC'11) keyed by (seed, site); slice l of
- *   sweep w uses word (l >> 6) of the block at counter (l & 63, w + offset, 2, 0);
+ *   sweep w uses word (l >> 6) of the block at counter (l & 63, w + offset, 2, c);
  *   initial field s_l uses the top bit of word (l >> 6) of the block at counter
- *   (l & 63, 0, 1, 0): 0 -> +1, 1 -> -1.  u = (x >> 11) * 2^-53.
+ *   (l & 63, 0, 1, c): 0 -> +1, 1 -> -1.  u = (x >> 11) * 2^-53.  c is the
+ *   chain index: independent chains of one impurity share its key and differ
+ *   in this counter word (c = 0 for a single chain).
  *   A from-scratch Dyson recompute replaces G after every `recompute_every`
  *   completed sweeps; then, once past the warm-up, every sweep is measured:
  *     n_sigma = 1 - (1/L) sum_l G_sigma[l][l]
@@ -61,6 +63,7 @@ typedef struct {
     uint64_t site;
     int64_t sweep_offset;     /* added to the sweep index in the RNG counter */
     const int8_t *init_fields; /* NULL: draw from the generator */
+    uint64_t chain;            /* chain index: counter word 3 of every draw */
 } ref_problem;
 
 typedef struct {
@@ -99,9 +102,9 @@ void ref_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-static uint64_t word_for(uint64_t seed, uint64_t site, int l, uint64_t c1, uint64_t purpose)
+static uint64_t word_for(uint64_t seed, uint64_t site, int l, uint64_t c1, uint64_t purpose, uint64_t chain)
 {
-    uint64_t ctr[4] = {(uint64_t)(l & 63), c1, purpose, 0};
+    uint64_t ctr[4] = {(uint64_t)(l & 63), c1, purpose, chain};
     uint64_t key[2] = {seed, site};
     uint64_t out[4];
     ref_philox4x64(ctr, key, out);
@@ -257,7 +260,7 @@ static int run_one(const ref_problem *p, ref_result *r)
 
     for (int l = 0; l < L; ++l) {
         if (p->init_fields) s[l] = p->init_fields[l] >= 0 ? 1 : -1;
-        else s[l] = (word_for(p->seed, p->site, l, 0, 1) >> 63) ? -1 : 1;
+        else s[l] = (word_for(p->seed, p->site, l, 0, 1, p->chain) >> 63) ? -1 : 1;
     }
     int rc = 0;
     for (int a = 0; a < 2 && !rc; ++a) rc = ref_dyson(L, gw[a], lam, a == 0 ? 1 : -1, s, G[a]);
@@ -269,7 +272,7 @@ static int run_one(const ref_problem *p, ref_result *r)
             double Ru = 1.0 + (1.0 - G[0][l * L + l]) * du;
             double Rd = 1.0 + (1.0 - G[1][l * L + l]) * dd;
             double R = Ru * Rd;
-            uint64_t x = word_for(p->seed, p->site, l, (uint64_t)(w + p->sweep_offset), 2);
+            uint64_t x = word_for(p->seed, p->site, l, (uint64_t)(w + p->sweep_offset), 2, p->chain);
             double u = (double)(x >> 11) * 0x1.0p-53;
             r->proposals++;
             if (!(R > 0)) { r->nonpositive++; continue; }

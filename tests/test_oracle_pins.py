@@ -262,3 +262,55 @@ def test_invalid_problem_is_rejected():
     p = wl.atom_problem(8, 2.0, 4.0, 1.0, n_measure=10, n_bins=32)
     r = oracle.run([p])[0]
     assert r["status"] == -1
+
+
+# ----------------------------------------------------------------- several chains per impurity
+def _np_philox_block(ctr, key):
+    c = list(ctr)
+    i = 0
+    while True:  # numpy's Philox emits philox(counter + 1, key) first
+        if c[i] > 0:
+            c[i] -= 1
+            break
+        c[i] = 2**64 - 1
+        i += 1
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+def test_chain_index_is_counter_word_three():
+    """With U = 0 every flip is accepted (R = 1 > u), so after two sweeps the
+    fields are the drawn initial ones: they must be the top bits of Philox
+    blocks at counter (l & 63, 0, 1, chain)."""
+    L, seed, site = 70, 11, 5
+    g = np.full(L, 0.5)
+    base = dict(L=L, beta=7.0, U=0.0, weiss=np.stack([g, g]), n_warmup=0, n_measure=2, n_bins=2, seed=seed,
+                site=site, recompute_every=50)
+    for chain in (0, 1, 7):
+        got = oracle.run([dict(base, chain=chain)])[0]["fields"]
+        want = np.array([-1 if (int(_np_philox_block([l & 63, 0, 1, chain], [seed, site])[l >> 6]) >> 63) else 1
+                         for l in range(L)], dtype=np.int8)
+        assert np.array_equal(got, want), chain
+
+
+def test_single_chain_pooling_is_the_plain_run():
+    p = wl.two_site_problem(8, 2.0, 4.0, 1.0, 0.8, 0.4, n_warmup=20, n_measure=300)
+    p["n_bins"] = 6
+    pooled, counts, parts = oracle.run_chains(p, 1)
+    plain = oracle.run([p])[0]
+    assert np.array_equal(parts[0]["fields"], plain["fields"])
+    assert np.max(np.abs(pooled - plain["bins"])) < 1e-14
+    assert counts.sum() == 300
+
+
+def test_pooled_chains_match_enumeration():
+    L, beta, U, mu, V, eb = 6, 2.0, 4.0, 1.0, 0.8, 0.4
+    p = wl.two_site_problem(L, beta, U, mu, V, eb, n_warmup=200, n_measure=40000, seed=3)
+    p["n_bins"] = 40
+    pooled, counts, parts = oracle.run_chains(p, 4, n_threads=4)
+    assert counts.sum() == 40000 and len({r["fields"].tobytes() for r in parts}) > 1  # chains differ
+    s = oracle.summarize(pooled, L)
+    lam = oracle.lam(beta / L, U)
+    vals, _, _ = ex.enumerate_fields(p["weiss"][0], p["weiss"][1], lam)
+    for key, idx in (("n_up", 2 * L + 2), ("n_dn", 2 * L + 3), ("docc", 2 * L + 4)):
+        assert abs(s[key] - vals[idx]) < 4.0 * s[key + "_err"] + 1e-12, key
