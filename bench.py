@@ -21,7 +21,8 @@ Other workloads (one JSON line each, --workload NAME or all):
            with their drift and g(tau) shift against the fp64 path
   serving  Poisson request stream (200/s), L in {20,40,80,160} (4:3:2:1),
            U = 8, dtau = 0.25, 5000 sweeps, 200 sites x 10 DMFT iterations
-           with device-resident state: p50/p99 latency and throughput
+           with device-resident state: p50/p99 latency and throughput;
+           --serve-chains N splits each L = 160 request into N chains
   trapped  21x21 trap (V0 = 0.05, U = 8, beta = 10, L = 40, AF seed), the
            325 sites with n > 1e-3, 1000 + 10000 sweeps, fp64
   slab     41x41 trap (V0 = 0.02, U = 8, beta = 16, L = 80, ~1000 atoms,
@@ -184,6 +185,9 @@ def bench_uneven(args):
 def bench_serving(args):
     from paper_1006_2716_amd import hfqmc, serve_load, workloads
     sites, arrivals, weiss = workloads.serving_requests()
+    for s in sites:  # the device-memory kernel class bounds the tail: split it into chains
+        if s["L"] > 128 and args.serve_chains > 1:
+            s["n_chains"] = args.serve_chains
     ctx = hfqmc.Context(0)
     ctx.attach_pool(1 << 30)
     ctx.serve_config(step_ms=args.step_ms, quantum_proposals=args.quantum)
@@ -197,7 +201,8 @@ def bench_serving(args):
     _line("HF-QMC serving: p99 request latency (Poisson 200 req/s)", out["p99_ms"], "ms", 1, 0, wall * 1e3,
           {"workload": "Poisson 200 req/s, L in {20,40,80,160} weights 4:3:2:1, U=8, dtau=0.25, 5000 sweeps "
                        "(500 warm-up first, 100 later), 200 sites x 10 DMFT iterations, state on device",
-           "step_ms": args.step_ms, "quantum_proposals": args.quantum, "steps": st["steps"],
+           "step_ms": args.step_ms, "quantum_proposals": args.quantum, "chains_L160": max(1, args.serve_chains),
+           "steps": st["steps"],
            "launches": st["launches"], "step_ms_avg": st["step_ms_avg"], "launch_ms_avg": st["launch_ms_avg"]},
           higher_is_better=False, serving=out)
 
@@ -246,6 +251,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the pass from a captured hipGraph")
     ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
     ap.add_argument("--quantum", type=int, default=0, help="serving: fixed proposals per request per step")
+    ap.add_argument("--serve-chains", type=int, default=1, help="serving: chains per L = 160 request")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()

@@ -23,8 +23,9 @@
  *     (seed, site_id); slice l of sweep w uses word (l >> 6) of the block at
  *     counter (l & 63, w + sweep_offset, 2, 0); u = (x >> 11) 2^-53.  Drawn
  *     initial fields use the top bit of word (l >> 6) at counter (l & 63, 0, 1, 0)
- *     (0 -> +1).  Results therefore depend only on the problem, never on the
- *     batch it runs in.
+ *     (0 -> +1).  Counter word 3 is the chain index (0 for a single chain).
+ *     Results therefore depend only on the problem, never on the batch it
+ *     runs in.
  *   - The Dyson equation G = [1 + (1 - G0)(e^V - 1)]^{-1} G0 is solved from
  *     scratch at the start and after every `recompute_every` sweeps; measured
  *     sweeps (after n_warmup) contribute g_sigma(tau_k) (k = 0..L, with
@@ -74,8 +75,8 @@ typedef struct hfqmc_ctx hfqmc_ctx;   /* opaque; one per device and stream */
 typedef struct hfqmc_site hfqmc_site; /* opaque device-resident impurity state */
 
 /* One impurity problem.  1 <= L <= 160, beta > 0, U >= 0, n_bins >= 2,
- * n_measure >= n_bins, recompute_every >= 1, Weiss samples finite with
- * g(0+) in (0, 1). */
+ * n_measure >= n_bins per chain, recompute_every >= 1, Weiss samples finite
+ * with g(0+) in (0, 1). */
 typedef struct {
     int32_t L;
     double beta;
@@ -97,6 +98,13 @@ typedef struct {
                                    L > 128 always runs delayed fp64 updates with
                                    G in device memory: delay 0 means 16, 1..16
                                    the depth, more is EINVAL */
+    int32_t n_chains;           /* independent Markov chains for this impurity
+                                   (0 or 1: one).  Chain j draws with Philox
+                                   counter word 3 = j, runs the full warm-up and
+                                   n_measure / n_chains measured sweeps (the first
+                                   n_measure % n_chains chains one more); bin b of
+                                   the result pools all chains' bin b.  At most
+                                   64; n_measure >= n_chains * n_bins. */
 } hfqmc_problem;
 
 /* Result of one impurity.  Pointer members are caller-owned and may be NULL. */
@@ -186,15 +194,19 @@ hfqmc_status hfqmc_plan(hfqmc_ctx *ctx, int32_t L, int32_t delay, int32_t *rt, i
 
 /* Give the context caller-owned device memory for site state and serving. */
 hfqmc_status hfqmc_attach_pool(hfqmc_ctx *ctx, void *d_pool, size_t bytes);
-/* Bytes of pool one site of L slices occupies (fields, G, bins, Weiss). */
-hfqmc_status hfqmc_site_bytes(int32_t L, int32_t n_bins, size_t *bytes);
-hfqmc_status hfqmc_site_open(hfqmc_ctx *ctx, int32_t L, int32_t n_bins, hfqmc_site **out);
+/* Bytes of pool one site of L slices and n_chains chains (0 or 1: one)
+ * occupies (per chain: fields, G, bins, Weiss). */
+hfqmc_status hfqmc_site_bytes(int32_t L, int32_t n_bins, int32_t n_chains, size_t *bytes);
+/* Open a site; its problems must have this L, n_bins and n_chains.  The test
+ * hooks below act on chain 0. */
+hfqmc_status hfqmc_site_open(hfqmc_ctx *ctx, int32_t L, int32_t n_bins, int32_t n_chains, hfqmc_site **out);
 hfqmc_status hfqmc_site_close(hfqmc_ctx *ctx, hfqmc_site *site);
 /* Upload the problem (Weiss, U, beta, seeds) without sweeping. */
 hfqmc_status hfqmc_site_define(hfqmc_ctx *ctx, hfqmc_site *site, const hfqmc_problem *problem);
 
 /* Deterministic test hooks (blocking).  set_fields: fields (L x +-1) and a
- * fresh Dyson solve.  force_flips: flip the listed slices in order, each
+ * fresh Dyson solve, on every chain of the site.  The others act on chain 0.
+ * force_flips: flip the listed slices in order, each
  * accepted unconditionally via Sherman-Morrison; ratios (n, may be NULL)
  * receive R_up R_dn of each flip.  get_green: G_spin as L x L row-major.
  * recompute: fresh Dyson solve; *drift (may be NULL) receives
@@ -208,9 +220,10 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drif
 
 /* ---- serving: continuous batching of impurity solves on sites ----
  * A library thread admits submitted requests while the CU shares of the
- * admitted ones (1 / resident workgroups per CU of the site's kernel) fit
- * the capacity, and advances all admitted requests together in steps: a
- * step launches every admitted request once, each kernel class on its own
+ * admitted ones (n_chains / resident workgroups per CU of the site's kernel)
+ * fit the capacity, and advances all admitted requests together in steps: a
+ * step launches every chain of every admitted request once (one workgroup
+ * per chain), each kernel class on its own
  * stream (classes run concurrently), with a per-class sweep count sized from
  * the class's time per proposal (a cost model of the kernel shape, measured
  * on MI355X) so that the step takes about `step_ms`.  Requests that arrive
@@ -228,7 +241,8 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx *ctx, hfqmc_site *site, double *drif
  * > 0 instead fixes the proposals per request per step (0: timed steps);
  * capacity_cus > 0 sets the admission capacity in CUs (0: all CUs). */
 hfqmc_status hfqmc_serve_config(hfqmc_ctx *ctx, double step_ms, int64_t quantum_proposals, double capacity_cus);
-/* Queue a request on a site (problem L and n_bins must match the site's).
+/* Queue a request on a site (problem L, n_bins and n_chains must match the
+ * site's).
  * Inputs are copied before the call returns.  EAGAIN: the site has a
  * request in progress, or the queue is full.  *ticket identifies it. */
 hfqmc_status hfqmc_submit(hfqmc_ctx *ctx, hfqmc_site *site, const hfqmc_problem *problem, uint64_t *ticket);

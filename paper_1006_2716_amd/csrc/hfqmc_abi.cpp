@@ -79,6 +79,7 @@ int padded_L(int L) { return (L + 15) / 16 * 16; }
 constexpr int kMaxDelay = 32;    // panel capacity of the delayed-update kernels
 constexpr int kAuxStreams = 3;   // extra streams for concurrent kernel classes
 constexpr int kSrvStreams = 6;   // serving launch streams
+constexpr int kMaxChains = 64;   // independent chains per problem
 
 // Kernel shape of one class: tile-rows per wave, update kind (0 plain
 // rank-one, 1 delayed fp64, 2 delayed mixed) and delay depth.
@@ -110,12 +111,23 @@ double coupling(double dtau, double U) {
   return std::log1p(m + std::sqrt(m * (m + 2.0)));
 }
 
+// Chains of one problem (0 and 1 both mean one) and the measured sweeps of
+// chain j: an equal share, the first n_measure % n_chains chains one more.
+int chains_of(const hfqmc_problem& p) { return p.n_chains > 1 ? p.n_chains : 1; }
+int64_t chain_measure(const hfqmc_problem& p, int j) {
+  const int nc = chains_of(p);
+  return p.n_measure / nc + (j < p.n_measure % nc ? 1 : 0);
+}
+
 hfqmc_status validate(const hfqmc_problem& p, int idx) {
   if (p.L < 1 || p.L > kMaxL) return fail(HFQMC_EINVAL, "problem %d: L=%d outside [1,%d]", idx, p.L, kMaxL);
   if (!(p.beta > 0) || !std::isfinite(p.beta)) return fail(HFQMC_EINVAL, "problem %d: beta must be > 0", idx);
   if (!(p.U >= 0) || !std::isfinite(p.U)) return fail(HFQMC_EINVAL, "problem %d: U must be >= 0", idx);
   if (p.n_bins < 2) return fail(HFQMC_EINVAL, "problem %d: n_bins must be >= 2", idx);
-  if (p.n_measure < p.n_bins) return fail(HFQMC_EINVAL, "problem %d: n_measure < n_bins", idx);
+  if (p.n_chains < 0 || p.n_chains > kMaxChains)
+    return fail(HFQMC_EINVAL, "problem %d: n_chains outside [0,%d]", idx, kMaxChains);
+  if (p.n_measure < (int64_t)chains_of(p) * p.n_bins)
+    return fail(HFQMC_EINVAL, "problem %d: n_measure < n_chains * n_bins", idx);
   if (p.n_warmup < 0) return fail(HFQMC_EINVAL, "problem %d: n_warmup < 0", idx);
   if (p.recompute_every < 1) return fail(HFQMC_EINVAL, "problem %d: recompute_every < 1", idx);
   if (p.delay < 0 || p.delay > kMaxDelay) return fail(HFQMC_EINVAL, "problem %d: delay outside [0,%d]", idx, kMaxDelay);
@@ -154,13 +166,27 @@ void fill_constants(ImpDesc& d, const hfqmc_problem& p) {
   d.delay = 1;
 }
 
-// Bin counts, means and errors from per-bin sums.
-void finalise(const hfqmc_problem& p, const double* sums, const ImpStatus& st, const int8_t* fields,
-              hfqmc_result& r) {
-  const int L = p.L, NV = n_values(L), nb = p.n_bins;
-  const int64_t nm = p.n_measure;
-  std::vector<int64_t> cnt(nb, 0);
+// Add the measurement count of each bin of a chain with nm measured sweeps
+// (sweep m falls in bin floor(m nb / nm)).
+void add_bin_counts(int64_t nm, int nb, int64_t* cnt) {
   for (int64_t m = 0; m < nm; ++m) cnt[(m * nb) / nm]++;
+}
+
+// Adds one chain's bin sums and status into the pooled ones.
+void pool_chain(int NV, int nb, const double* sums, const ImpStatus& st, double* psums, ImpStatus& pst) {
+  for (size_t k = 0; k < (size_t)nb * NV; ++k) psums[k] += sums[k];
+  pst.proposals += st.proposals;
+  pst.accepts += st.accepts;
+  pst.nonpositive += st.nonpositive;
+  pst.error |= st.error;
+  pst.max_drift = std::max(pst.max_drift, st.max_drift);
+}
+
+// Bin means and errors from per-bin sums and measurement counts (pooled over
+// the chains of the problem).
+void finalise(int L, int nb, const double* sums, const int64_t* cnt, const ImpStatus& st, const int8_t* fields,
+              hfqmc_result& r) {
+  const int NV = n_values(L);
   std::vector<double> mean(NV, 0.0), err(NV, 0.0), bm((size_t)nb * NV);
   for (int b = 0; b < nb; ++b)
     for (int v = 0; v < NV; ++v) bm[(size_t)b * NV + v] = sums[(size_t)b * NV + v] / (double)cnt[b];
@@ -225,6 +251,27 @@ struct Group {
   int LT, rt, dk;
   int first, count, grid;
 };
+
+// A batch with every problem split into its chains: item k runs chain
+// chain[k] of problem owner[k], with that chain's measured sweeps.
+struct Expanded {
+  std::vector<hfqmc_problem> items;
+  std::vector<int> owner, chain;
+};
+
+Expanded expand(const hfqmc_problem* p, int n) {
+  Expanded e;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < chains_of(p[i]); ++j) {
+      hfqmc_problem q = p[i];
+      q.n_measure = chain_measure(p[i], j);
+      q.n_chains = 1;
+      e.items.push_back(q);
+      e.owner.push_back(i);
+      e.chain.push_back(j);
+    }
+  return e;
+}
 
 // Workspace layout of one batch.
 struct Layout {
@@ -395,9 +442,14 @@ bool write_tune_cache(const std::string& path, const std::vector<TuneEntry>& v) 
 
 struct hfqmc_site {
   int L, LT, RT, n_bins;
+  int n_chains = 1;
   int DK = 0, K = 1;  // update kind and delay depth of the site's kernel
   size_t off, bytes;  // pool block
-  size_t o_desc, o_weiss, o_init, o_fields, o_bins, o_status, o_state, o_force, o_queue;
+  // shared by the chains: descriptor, Weiss, initial fields, forced-flip
+  // buffer, queue; per chain (chain 0's offsets, then + j * chain_stride):
+  // fields, status, bins, state
+  size_t o_desc, o_weiss, o_init, o_force, o_queue;
+  size_t o_fields, o_bins, o_status, o_state, chain_stride;
   bool defined = false, has_state = false;
   bool busy = false;  // a serving request owns the site (guarded by the server mutex)
   hfqmc_problem prob{};
@@ -411,7 +463,8 @@ struct Request {
   uint64_t ticket = 0;
   hfqmc_site* site = nullptr;
   hfqmc_problem prob{};
-  int64_t total = 0, done = 0, q = 0;
+  // per chain: sweeps in all, sweeps done, sweeps of the step in flight
+  std::vector<int64_t> total, done, q;
   int state = R_PENDING;
   bool first = true, given = false, keep = false, cancel = false;
   double weight = 0.0;
@@ -472,7 +525,9 @@ struct hfqmc_ctx {
   bool staged = false;
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
-  std::vector<hfqmc_problem> probs;
+  std::vector<hfqmc_problem> probs;  // as given (n_chains chains each)
+  std::vector<int> item_owner, item_chain;  // work item -> (problem, chain)
+  std::vector<int64_t> item_measure;        // measured sweeps of each item
   std::vector<Group> groups;
   Layout lo;
   hipStream_t aux[kAuxStreams] = {};
@@ -582,8 +637,12 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
 // Stage a batch: group by kernel class (padded L, shape), order items inside
 // a class by descending work, upload descriptors and inputs.  `force`, when
 // set, overrides the plan of every problem (autotuning).
-hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws, size_t ws_bytes, const Plan* force) {
-  for (int i = 0; i < n; ++i) TRY(validate(p[i], i));
+hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_ws, size_t ws_bytes,
+                        const Plan* force) {
+  for (int i = 0; i < n0; ++i) TRY(validate(p0[i], i));
+  const Expanded ex = expand(p0, n0);  // from here on a work item is one chain
+  const hfqmc_problem* p = ex.items.data();
+  const int n = (int)ex.items.size();
   Layout lo = plan_layout(p, n);
   if (ws_bytes < lo.total) return fail(HFQMC_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, lo.total);
   TRY(set_device(c));
@@ -600,10 +659,10 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws,
     idx[i] = i;
     plan[i] = force ? *force : plan_for(c, p[i]);
     if (plan[i].rt == 0 && plan[i].k > kGlobalMaxDelay)
-      return fail(HFQMC_EINVAL, "problem %d: delay %d > %d for L=%d", i, plan[i].k, kGlobalMaxDelay, p[i].L);
+      return fail(HFQMC_EINVAL, "problem %d: delay %d > %d for L=%d", ex.owner[i], plan[i].k, kGlobalMaxDelay, p[i].L);
     if (!find_kernel(padded_L(p[i].L), plan[i].rt, plan[i].dk))
-      return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", i, plan[i].dk ? "delayed-update" : "sweep",
-                  p[i].L);
+      return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", ex.owner[i],
+                  plan[i].dk ? "delayed-update" : "sweep", p[i].L);
   }
   // expected work: sweeps x L proposals, a fraction exp(-0.76 lambda^2) of
   // them accepted (fits the measured acceptance of the chain workloads at
@@ -653,6 +712,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws,
     d.off_status = (int64_t)(lo.status + sizeof(ImpStatus) * i);
     d.off_state = (int64_t)lo.s_off[i];
     d.off_force = 0;
+    d.chain = ex.chain[i];
     descs[i] = d;
     std::memcpy(img.data() + lo.w_off[i], p[i].weiss[0], sizeof(double) * p[i].L);
     std::memcpy(img.data() + lo.w_off[i] + sizeof(double) * p[i].L, p[i].weiss[1], sizeof(double) * p[i].L);
@@ -663,8 +723,12 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p, int n, void* d_ws,
   c->ws_bytes = ws_bytes;
   HIP_TRY(hipMemcpyAsync(c->ws, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->probs.assign(p, p + n);
+  c->probs.assign(p0, p0 + n0);
   for (auto& q : c->probs) q.weiss[0] = q.weiss[1] = nullptr, q.init_fields = nullptr;
+  c->item_owner = ex.owner;
+  c->item_chain = ex.chain;
+  c->item_measure.resize(n);
+  for (int i = 0; i < n; ++i) c->item_measure[i] = p[i].n_measure;
   c->groups = groups;
   c->lo = lo;
   c->staged = true;
@@ -722,6 +786,11 @@ size_t site_layout(hfqmc_site* s) {
   off = align_up(off + sizeof(double) * 2 * s->L, 256);
   s->o_init = off;
   off = align_up(off + s->L, 256);
+  s->o_force = off;
+  off = align_up(off + 1024 * (sizeof(int32_t) + sizeof(double)), 256);
+  s->o_queue = off;  // queue counter + order entry
+  off = align_up(off + 256, 256);
+  const size_t chain0 = off;
   s->o_fields = off;
   off = align_up(off + s->L, 256);
   s->o_status = off;
@@ -730,29 +799,28 @@ size_t site_layout(hfqmc_site* s) {
   off = align_up(off + sizeof(double) * (size_t)s->n_bins * n_values(s->L), 256);
   s->o_state = off;
   off = align_up(off + state_bytes(s->L), 256);
-  s->o_force = off;
-  off = align_up(off + 1024 * (sizeof(int32_t) + sizeof(double)), 256);
-  s->o_queue = off;  // queue counter + order entry
-  off = align_up(off + 256, 256);
-  return off;
+  s->chain_stride = off - chain0;
+  return chain0 + s->chain_stride * s->n_chains;
 }
 
-void site_offsets(const hfqmc_site* s, ImpDesc& d) {
+void site_offsets(const hfqmc_site* s, ImpDesc& d, int chain = 0) {
+  const size_t cj = s->off + s->chain_stride * chain;
   d.off_weiss = (int64_t)(s->off + s->o_weiss);
   d.off_init = (int64_t)(s->off + s->o_init);
-  d.off_fields = (int64_t)(s->off + s->o_fields);
-  d.off_bins = (int64_t)(s->off + s->o_bins);
-  d.off_status = (int64_t)(s->off + s->o_status);
-  d.off_state = (int64_t)(s->off + s->o_state);
+  d.off_fields = (int64_t)(cj + s->o_fields);
+  d.off_bins = (int64_t)(cj + s->o_bins);
+  d.off_status = (int64_t)(cj + s->o_status);
+  d.off_state = (int64_t)(cj + s->o_state);
   d.off_force = (int64_t)(s->off + s->o_force);
   d.LT = s->LT;
   d.delay = s->K;
+  d.chain = chain;
 }
 
-// Launch one work item on a site (blocking, context stream).
-hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d) {
+// Launch one work item on chain `chain` of a site (blocking, context stream).
+hfqmc_status site_launch(hfqmc_ctx* c, hfqmc_site* s, ImpDesc d, int chain = 0) {
   uint8_t* base = c->pool + s->off;
-  site_offsets(s, d);
+  site_offsets(s, d, chain);
   const KernelInfo* k = find_kernel(s->LT, s->RT, s->DK);
   if (!k) return fail(HFQMC_EINVAL, "no kernel for LT=%d RT=%d", s->LT, s->RT);
   struct {
@@ -775,19 +843,30 @@ int site_bpc(const hfqmc_site* s) {
   return bpc;
 }
 
-// Copy a finished request's bins, status and fields back and finalise them.
+// Copy a finished request's bins, status and fields back, pool its chains
+// and finalise them.
 hfqmc_status srv_finish(hfqmc_ctx* c, Request* r) {
   Server& S = c->srv;
   hfqmc_site* s = r->site;
-  const int L = s->L, NV = n_values(L);
-  std::vector<double> sums((size_t)s->n_bins * NV);
+  const int L = s->L, NV = n_values(L), nb = s->n_bins, nc = s->n_chains;
+  std::vector<double> part((size_t)nc * nb * NV), sums((size_t)nb * NV, 0.0);
+  std::vector<ImpStatus> parts(nc);
+  std::vector<int64_t> cnt(nb, 0);
   ImpStatus st{};
   r->fields.resize(L);
   uint8_t* base = c->pool + s->off;
-  HIP_TRY(hipMemcpyAsync(sums.data(), base + s->o_bins, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, S.io));
-  HIP_TRY(hipMemcpyAsync(&st, base + s->o_status, sizeof st, hipMemcpyDeviceToHost, S.io));
+  for (int j = 0; j < nc; ++j) {
+    const size_t cj = s->chain_stride * j;
+    HIP_TRY(hipMemcpyAsync(&part[(size_t)j * nb * NV], base + cj + s->o_bins, sizeof(double) * nb * NV,
+                           hipMemcpyDeviceToHost, S.io));
+    HIP_TRY(hipMemcpyAsync(&parts[j], base + cj + s->o_status, sizeof(ImpStatus), hipMemcpyDeviceToHost, S.io));
+  }
   HIP_TRY(hipMemcpyAsync(r->fields.data(), base + s->o_fields, L, hipMemcpyDeviceToHost, S.io));
   HIP_TRY(hipStreamSynchronize(S.io));
+  for (int j = 0; j < nc; ++j) {
+    pool_chain(NV, nb, &part[(size_t)j * nb * NV], parts[j], sums.data(), st);
+    add_bin_counts(chain_measure(r->prob, j), nb, cnt.data());
+  }
   for (int k = 0; k < 2; ++k) {
     r->g[k].assign(L + 1, 0.0);
     r->gerr[k].assign(L + 1, 0.0);
@@ -797,7 +876,7 @@ hfqmc_status srv_finish(hfqmc_ctx* c, Request* r) {
   r->bins.assign(sums.size(), 0.0);
   r->res.bins = r->bins.data();
   r->res.final_fields = nullptr;
-  finalise(r->prob, sums.data(), st, r->fields.data(), r->res);
+  finalise(L, nb, sums.data(), cnt.data(), st, r->fields.data(), r->res);
   r->status = (hfqmc_status)r->res.status;
   return HFQMC_OK;
 }
@@ -838,9 +917,13 @@ bool srv_step(hfqmc_ctx* c) {
       if (!S.failed && hipEventElapsedTime(&ms, S.ev_begin[L.slot], S.ev_end[L.slot]) == hipSuccess)
         S.kernel_ms_sum += ms;
       for (Request* r : L.items) {
-        r->done += r->q;
+        bool finished = true;
+        for (size_t j = 0; j < r->q.size(); ++j) {
+          r->done[j] += r->q[j];
+          r->q[j] = 0;
+          finished = finished && r->done[j] >= r->total[j];
+        }
         r->first = false;
-        r->q = 0;
         if (r->cancel) {
           S.used -= r->weight;
           r->site->busy = false;
@@ -848,7 +931,7 @@ bool srv_step(hfqmc_ctx* c) {
           S.tickets.erase(r->ticket);
           ++S.cancelled;
           delete r;
-        } else if (S.failed || r->done >= r->total) {
+        } else if (S.failed || finished) {
           S.used -= r->weight;
           if (S.failed) {
             r->status = HFQMC_EDEVICE;
@@ -905,36 +988,49 @@ bool srv_step(hfqmc_ctx* c) {
       left.insert(left.end(), v.begin(), v.end());
       continue;
     }
-    if ((int)v.size() > S.max_items) {
-      left.insert(left.end(), v.begin() + S.max_items, v.end());
-      v.resize(S.max_items);
+    // one work item per unfinished chain; a request's chains go together
+    size_t take = 0;
+    int n = 0;
+    for (; take < v.size(); ++take) {
+      int u = 0;
+      for (size_t j = 0; j < v[take]->total.size(); ++j) u += v[take]->done[j] < v[take]->total[j];
+      if (n + u > S.max_items && take > 0) break;
+      n += u;
+    }
+    if (take < v.size()) {
+      left.insert(left.end(), v.begin() + take, v.end());
+      v.resize(take);
     }
     const hfqmc_site* head = v.front()->site;
     Launch L{slot, head->LT, head->RT, head->DK, head->K, 0, v};
     const double us = model_us_per_proposal(head);
-    const int n = (int)v.size();
     uint8_t* img = S.host_img[slot];
     ImpDesc* descs = reinterpret_cast<ImpDesc*>(img);
     int32_t* order = reinterpret_cast<int32_t*>(img + align_up(sizeof(ImpDesc) * S.max_items, 256));
     int32_t* queue = order + S.max_items;
-    for (int i = 0; i < n; ++i) {
-      Request* r = v[i];
-      ImpDesc d{};
-      fill_constants(d, r->prob);
-      site_offsets(r->site, d);
-      d.op = OP_SWEEPS;
-      const int64_t props = S.quantum > 0 ? S.quantum : (int64_t)(1e3 * S.step_ms / us);
+    const int64_t props = S.quantum > 0 ? S.quantum : (int64_t)(1e3 * S.step_ms / us);
+    int i = 0;
+    for (Request* r : v) {
       const int64_t q = std::max<int64_t>(1, props / r->site->L);
-      r->q = std::min(q, r->total - r->done);
-      L.max_props = std::max(L.max_props, r->q * r->site->L);
-      d.sweep_begin = r->done;
-      d.sweep_end = r->done + r->q;
-      if (r->first)
-        d.flags = F_ZERO_ACC | F_SAVE | (r->given ? F_FIELDS_GIVEN : (r->keep ? F_KEEP_FIELDS : 0));
-      else
-        d.flags = F_RESUME | F_SAVE;
-      descs[i] = d;
-      order[i] = i;
+      for (int j = 0; j < (int)r->total.size(); ++j) {
+        r->q[j] = std::min(q, r->total[j] - r->done[j]);
+        if (r->q[j] == 0) continue;
+        ImpDesc d{};
+        fill_constants(d, r->prob);
+        site_offsets(r->site, d, j);
+        d.op = OP_SWEEPS;
+        d.n_measure = chain_measure(r->prob, j);
+        L.max_props = std::max(L.max_props, r->q[j] * r->site->L);
+        d.sweep_begin = r->done[j];
+        d.sweep_end = r->done[j] + r->q[j];
+        if (r->first)
+          d.flags = F_ZERO_ACC | F_SAVE | (r->given ? F_FIELDS_GIVEN : (r->keep ? F_KEEP_FIELDS : 0));
+        else
+          d.flags = F_RESUME | F_SAVE;
+        descs[i] = d;
+        order[i] = i;
+        ++i;
+      }
       r->state = R_INFLIGHT;
     }
     *queue = 0;
@@ -1102,7 +1198,8 @@ const char* hfqmc_last_error(const hfqmc_ctx*) { return t_err.c_str(); }
 hfqmc_status hfqmc_workspace_size(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, size_t* bytes) {
   if (!c || !bytes || n < 0 || (n > 0 && !p)) return fail(HFQMC_EINVAL, "hfqmc_workspace_size: bad arguments");
   for (int i = 0; i < n; ++i) TRY(validate(p[i], i));
-  *bytes = plan_layout(p, n).total;
+  const Expanded ex = expand(p, n);
+  *bytes = plan_layout(ex.items.data(), (int)ex.items.size()).total;
   return HFQMC_OK;
 }
 
@@ -1183,13 +1280,23 @@ hfqmc_status hfqmc_collect(hfqmc_ctx* c, hfqmc_result* out) {
   HIP_TRY(hipMemcpyAsync(host.data(), c->ws + lo_off, hi_off - lo_off, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   hfqmc_status worst = HFQMC_OK;
-  for (size_t i = 0; i < c->probs.size(); ++i) {
+  // items of one problem are consecutive, chain 0 first
+  const size_t n_items = c->item_owner.size();
+  for (size_t k = 0; k < n_items;) {
+    const int i = c->item_owner[k];
     const hfqmc_problem& p = c->probs[i];
-    const double* sums = reinterpret_cast<const double*>(host.data() + (c->lo.b_off[i] - lo_off));
-    const ImpStatus* st =
-        reinterpret_cast<const ImpStatus*>(host.data() + (c->lo.status - lo_off) + sizeof(ImpStatus) * i);
-    const int8_t* fields = reinterpret_cast<const int8_t*>(host.data() + (c->lo.f_off[i] - lo_off));
-    finalise(p, sums, *st, fields, out[i]);
+    const int NV = n_values(p.L), nb = p.n_bins;
+    std::vector<double> sums((size_t)nb * NV, 0.0);
+    std::vector<int64_t> cnt(nb, 0);
+    ImpStatus st{};
+    const int8_t* fields = reinterpret_cast<const int8_t*>(host.data() + (c->lo.f_off[k] - lo_off));
+    for (; k < n_items && c->item_owner[k] == i; ++k) {
+      pool_chain(NV, nb, reinterpret_cast<const double*>(host.data() + (c->lo.b_off[k] - lo_off)),
+                 *reinterpret_cast<const ImpStatus*>(host.data() + (c->lo.status - lo_off) + sizeof(ImpStatus) * k),
+                 sums.data(), st);
+      add_bin_counts(c->item_measure[k], nb, cnt.data());
+    }
+    finalise(p.L, nb, sums.data(), cnt.data(), st, fields, out[i]);
     if (out[i].status != HFQMC_OK) worst = (hfqmc_status)out[i].status;
   }
   if (worst != HFQMC_OK) return fail(worst, "non-finite ratio or Green function in at least one impurity");
@@ -1224,10 +1331,10 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
       if (padded_L(p[i].L) == LT) {
         hfqmc_problem q = p[i];
         q.n_warmup = sweeps / 2;
-        q.n_measure = sweeps - sweeps / 2;
+        q.n_measure = (int64_t)(sweeps - sweeps / 2) * chains_of(q);
         q.n_bins = 2;
         sample.push_back(q);
-        props += (int64_t)sweeps * q.L;
+        props += (int64_t)sweeps * q.L * chains_of(q);
       }
     std::vector<Plan> cands;
     int rts[16];
@@ -1303,18 +1410,21 @@ hfqmc_status hfqmc_attach_pool(hfqmc_ctx* c, void* d_pool, size_t bytes) {
   return HFQMC_OK;
 }
 
-hfqmc_status hfqmc_site_bytes(int32_t L, int32_t n_bins, size_t* bytes) {
-  if (L < 1 || L > kMaxL || n_bins < 2 || !bytes) return fail(HFQMC_EINVAL, "hfqmc_site_bytes: bad arguments");
+hfqmc_status hfqmc_site_bytes(int32_t L, int32_t n_bins, int32_t n_chains, size_t* bytes) {
+  if (L < 1 || L > kMaxL || n_bins < 2 || n_chains < 0 || n_chains > kMaxChains || !bytes)
+    return fail(HFQMC_EINVAL, "hfqmc_site_bytes: bad arguments");
   hfqmc_site s;
   s.L = L;
   s.LT = padded_L(L);
   s.n_bins = n_bins;
+  s.n_chains = std::max(1, n_chains);
   *bytes = site_layout(&s);
   return HFQMC_OK;
 }
 
-hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, hfqmc_site** out) {
-  if (!c || !out || L < 1 || L > kMaxL || n_bins < 2) return fail(HFQMC_EINVAL, "hfqmc_site_open: bad arguments");
+hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, int32_t n_chains, hfqmc_site** out) {
+  if (!c || !out || L < 1 || L > kMaxL || n_bins < 2 || n_chains < 0 || n_chains > kMaxChains)
+    return fail(HFQMC_EINVAL, "hfqmc_site_open: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!c->pool) return fail(HFQMC_EINVAL, "hfqmc_site_open: no pool attached");
   hfqmc_site* s = new (std::nothrow) hfqmc_site;
@@ -1329,6 +1439,7 @@ hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, hfqmc_site
   s->DK = pl.dk;
   s->K = pl.k;
   s->n_bins = n_bins;
+  s->n_chains = std::max(1, n_chains);
   s->bytes = site_layout(s);
   if (hfqmc_status st = pool_alloc(c, s->bytes, &s->off)) {
     delete s;
@@ -1370,7 +1481,8 @@ hfqmc_status hfqmc_site_define(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem*
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
   if (site_busy(c, s)) return fail(HFQMC_EAGAIN, "site has a serving request in progress");
-  if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
+  if (p->L != s->L || p->n_bins != s->n_bins || chains_of(*p) != s->n_chains)
+    return fail(HFQMC_EINVAL, "problem L/n_bins/n_chains differ from the site's");
   TRY(validate(*p, 0));
   TRY(set_device(c));
   return site_upload_problem(c, s, p, c->stream);
@@ -1391,7 +1503,7 @@ hfqmc_status hfqmc_site_set_fields(hfqmc_ctx* c, hfqmc_site* s, const int8_t* fi
   d.op = OP_FORCE;
   d.n_force = 0;
   d.flags = F_FIELDS_GIVEN | F_SAVE | F_ZERO_ACC;
-  TRY(site_launch(c, s, d));
+  for (int j = 0; j < s->n_chains; ++j) TRY(site_launch(c, s, d, j));  // every chain starts here
   s->has_state = true;
   return HFQMC_OK;
 }
@@ -1486,7 +1598,8 @@ hfqmc_status hfqmc_submit(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p, u
   if (!c || !s || !p || !ticket) return fail(HFQMC_EINVAL, "hfqmc_submit: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   if (!site_known(c, s)) return fail(HFQMC_ENOTFOUND, "unknown site");
-  if (p->L != s->L || p->n_bins != s->n_bins) return fail(HFQMC_EINVAL, "problem L/n_bins differ from the site's");
+  if (p->L != s->L || p->n_bins != s->n_bins || chains_of(*p) != s->n_chains)
+    return fail(HFQMC_EINVAL, "problem L/n_bins/n_chains differ from the site's");
   TRY(validate(*p, 0));
   TRY(srv_start(c));
   Server& S = c->srv;
@@ -1511,10 +1624,12 @@ hfqmc_status hfqmc_submit(hfqmc_ctx* c, hfqmc_site* s, const hfqmc_problem* p, u
   }
   r->site = s;
   r->prob = s->prob;
-  r->total = p->n_warmup + p->n_measure;
+  for (int j = 0; j < s->n_chains; ++j) r->total.push_back(p->n_warmup + chain_measure(*p, j));
+  r->done.assign(s->n_chains, 0);
+  r->q.assign(s->n_chains, 0);
   r->given = p->init_fields != nullptr;
   r->keep = !r->given && had_state;
-  r->weight = 1.0 / site_bpc(s);
+  r->weight = (double)s->n_chains / site_bpc(s);
   {
     std::lock_guard<std::mutex> gs(S.mu);
     r->ticket = S.next_ticket++;

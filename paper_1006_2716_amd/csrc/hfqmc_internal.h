@@ -61,7 +61,7 @@ struct alignas(16) ImpDesc {
                             // snapshot (global kernel) or parked bin sums (register kernels)
   int64_t off_force;        // OP_FORCE: n_force int32 slices, then n_force doubles ratios
   int64_t off_init;         // F_FIELDS_GIVEN: L int8 initial fields (read only)
-  int64_t pad_;
+  int64_t chain;            // chain index of this impurity: Philox counter word 3
 };
 
 struct alignas(16) ImpStatus {

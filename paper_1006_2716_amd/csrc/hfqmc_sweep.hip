@@ -492,7 +492,7 @@ struct Engine : SliceState<C::JW> {
         set_field(jj, m < L ? (fin[m] < 0 ? -1 : 1) : 1);
       });
     } else {
-      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, 0, d.seed, d.site);
+      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, (uint64_t)d.chain, d.seed, d.site);
       static_for<JW>([&](auto jj) __attribute__((always_inline)) { set_field(jj, (x.v[jj] >> 63) ? -1 : 1); });
     }
     __syncthreads();
@@ -543,8 +543,8 @@ struct Engine : SliceState<C::JW> {
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
         double uv[JW];
         {
-          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep, 0, d.seed,
-                                        d.site);
+          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
+                                        (uint64_t)d.chain, d.seed, d.site);
           static_for<JW>([&](auto jj) __attribute__((always_inline)) { uv[jj] = u01(x.v[jj]); });
         }
         double fu, fd;

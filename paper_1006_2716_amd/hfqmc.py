@@ -32,7 +32,7 @@ class Problem(C.Structure):
         ("n_warmup", C.c_int64), ("n_measure", C.c_int64),
         ("recompute_every", C.c_int32), ("n_bins", C.c_int32),
         ("seed", C.c_uint64), ("site_id", C.c_uint64), ("sweep_offset", C.c_int64),
-        ("init_fields", C.POINTER(C.c_int8)), ("delay", C.c_int32),
+        ("init_fields", C.POINTER(C.c_int8)), ("delay", C.c_int32), ("n_chains", C.c_int32),
     ]
 
 
@@ -79,8 +79,8 @@ def lib():
             "hfqmc_collect": [_VP, C.POINTER(Result)],
             "hfqmc_last_run_ms": [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
             "hfqmc_attach_pool": [_VP, _VP, C.c_size_t],
-            "hfqmc_site_bytes": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
-            "hfqmc_site_open": [_VP, C.c_int32, C.c_int32, C.POINTER(_VP)],
+            "hfqmc_site_bytes": [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+            "hfqmc_site_open": [_VP, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_VP)],
             "hfqmc_site_close": [_VP, _VP],
             "hfqmc_site_define": [_VP, _VP, C.POINTER(Problem)],
             "hfqmc_site_set_fields": [_VP, _VP, C.POINTER(C.c_int8)],
@@ -157,6 +157,7 @@ class _Problems:
             pr.sweep_offset = int(p.get("sweep_offset", 0))
             pr.init_fields = None if ia is None else ia.ctypes.data_as(C.POINTER(C.c_int8))
             pr.delay = int(p.get("delay", 0))
+            pr.n_chains = int(p.get("n_chains", 0))
         self.n = n
 
 
@@ -337,24 +338,25 @@ class Context:
         _check(lib().hfqmc_attach_pool(self.h, _VP(self._pool.data_ptr()), int(nbytes)), "hfqmc_attach_pool")
         return self._pool
 
-    def site(self, L: int, n_bins: int = 32):
-        return Site(self, L, n_bins)
+    def site(self, L: int, n_bins: int = 32, n_chains: int = 1):
+        return Site(self, L, n_bins, n_chains)
 
 
-def site_bytes(L: int, n_bins: int = 32) -> int:
+def site_bytes(L: int, n_bins: int = 32, n_chains: int = 1) -> int:
     b = C.c_size_t()
-    _check(lib().hfqmc_site_bytes(L, n_bins, C.byref(b)), "hfqmc_site_bytes")
+    _check(lib().hfqmc_site_bytes(L, n_bins, n_chains, C.byref(b)), "hfqmc_site_bytes")
     return b.value
 
 
 class Site:
     """Device-resident impurity state (fields and Green matrices) in the context pool."""
 
-    def __init__(self, ctx: Context, L: int, n_bins: int = 32):
+    def __init__(self, ctx: Context, L: int, n_bins: int = 32, n_chains: int = 1):
         self.ctx = ctx
         self.L = L
+        self.n_chains = n_chains
         h = _VP()
-        _check(lib().hfqmc_site_open(ctx.h, L, n_bins, C.byref(h)), "hfqmc_site_open")
+        _check(lib().hfqmc_site_open(ctx.h, L, n_bins, n_chains, C.byref(h)), "hfqmc_site_open")
         self.h = h
 
     def close(self):

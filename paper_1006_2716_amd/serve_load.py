@@ -14,11 +14,13 @@ import numpy as np
 
 
 def site_request(site: dict, it: int, weiss, sweeps: int, warm_first: int, warm_next: int, n_bins: int = 32) -> dict:
-    """Problem dict of iteration `it` of a site (see workloads.serving_requests)."""
+    """Problem dict of iteration `it` of a site (see workloads.serving_requests).
+    A site with "n_chains" > 1 runs that many chains, each with the full
+    warm-up and a share of the measured sweeps."""
     nw = warm_first if it == 0 else warm_next
     return dict(L=site["L"], beta=site["beta"], U=site["U"], weiss=weiss(site, it), n_warmup=nw,
                 n_measure=sweeps - nw, recompute_every=50, n_bins=n_bins, seed=site["seed"], site=site["site"],
-                sweep_offset=it * sweeps, delay=0)
+                sweep_offset=it * sweeps, delay=0, n_chains=site.get("n_chains", 1))
 
 
 def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, warm_first: int = 500,
@@ -28,7 +30,7 @@ def replay(ctx, sites, arrivals, weiss, n_iter: int = 10, sweeps: int = 5000, wa
 
     Returns latency percentiles (ms), throughput (proposals/s over the
     makespan), per-L latency medians and the per-request results."""
-    handles = [ctx.site(s["L"], n_bins=n_bins) for s in sites]
+    handles = [ctx.site(s["L"], n_bins=n_bins, n_chains=s.get("n_chains", 1)) for s in sites]
     n = len(sites)
     it = [0] * n
     due = list(np.asarray(arrivals, dtype=float))

@@ -58,6 +58,19 @@ def test_site_bytes_grows_with_L():
         hfqmc.site_bytes(0)
 
 
+def test_site_bytes_per_chain():
+    one = hfqmc.site_bytes(96, 16)
+    assert hfqmc.site_bytes(96, 16, 0) == one  # 0 and 1 both mean one chain
+    four = hfqmc.site_bytes(96, 16, 4)
+    # every chain holds its own G, fields, bins and status; Weiss and buffers are shared
+    per_chain = four - one
+    assert per_chain % 3 == 0 and per_chain // 3 >= 4 * 96 * 96 * 8
+    assert four < 4 * one
+    for bad in (-1, 65):
+        with pytest.raises(hfqmc.HFQMCError):
+            hfqmc.site_bytes(96, 16, bad)
+
+
 def test_null_context_is_rejected():
     lib = hfqmc.lib()
     assert lib.hfqmc_workspace_size(None, None, 0, None) == hfqmc.EINVAL
