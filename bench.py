@@ -48,8 +48,8 @@ RECOMPUTE_EVERY = 50
 # HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
 # FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
 # valid only for the kernel source with this sha256 prefix.
-PROFILED_KERNEL_SHA = "6a524ae184108749"
-PROFILED_TRAFFIC_BYTES = 1.726e9
+PROFILED_KERNEL_SHA = "1c496bc5fa2fbc3e"
+PROFILED_TRAFFIC_BYTES = 1.838e9
 
 
 def kernel_sha() -> str:
