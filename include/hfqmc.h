@@ -265,6 +265,71 @@ typedef struct {
 } hfqmc_serve_stats_t;
 hfqmc_status hfqmc_serve_stats(hfqmc_ctx *ctx, hfqmc_serve_stats_t *out);
 
+/* ---- real-space DMFT self-consistency around the solver ----
+ * The lattice Dyson equation, Eq. (2) (site-diagonal self-energy, one inverse
+ * per Matsubara frequency and spin), the impurity Dyson equation linking the
+ * local Green function, self-energy and Weiss function of each site, and the
+ * transforms between Matsubara frequencies w_n = (2n + 1) pi / beta
+ * (n < n_freq) and the solver's time slices.
+ *
+ * Conventions.  Spin s = 0 (up), 1 (down).  The one-body matrix of spin s is
+ * hop + diag(eps_s): hop real symmetric (hopping amplitudes; the paper's
+ * t_ij enters with the opposite sign), eps_s the site energies (trap
+ * potential, seed fields).  mu is the chemical potential of the
+ * Hartree-shifted levels the solver takes (mu - U/2 in the paper's
+ * notation) and sigma the self-energy relative to them (Sigma - U/2), so that
+ * sigma = 0 gives the U = 0 lattice.  Complex arrays are interleaved (re, im)
+ * doubles; a "spin-frequency-site" array holds element (s, n, i) at
+ * (s * n_freq + n) * n_sites + i.  Every array argument named d_* is device
+ * memory owned by the caller; all calls are asynchronous on the context's
+ * stream and allocate nothing except where stated.
+ *
+ * Lattice structure.  Sites are numbered layer by layer (n_sites = n_layers x
+ * layer, 1 <= layer <= 64); hop may couple sites inside a layer arbitrarily,
+ * and site j of layer k only with site j of layers k +- 1 (a square lattice
+ * numbered row by row, with the row as the layer).  Anything else is EINVAL. */
+typedef struct hfqmc_lattice hfqmc_lattice; /* opaque: hopping blocks on the device */
+
+/* Validates and uploads hop (host, n_sites x n_sites row-major); allocates
+ * the lattice's device copy (freed by destroy). */
+hfqmc_status hfqmc_lattice_create(hfqmc_ctx *ctx, int32_t n_sites, int32_t layer, const double *hop,
+                                  hfqmc_lattice **out);
+hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx *ctx, hfqmc_lattice *lat);
+/* Device workspace of hfqmc_lattice_green for n_freq frequencies
+ * (1 <= n_freq <= 2048): 2 n_freq n_layers P^2 complex doubles, P the layer
+ * width padded to 16, 32, 48 or 64. */
+hfqmc_status hfqmc_lattice_workspace(const hfqmc_lattice *lat, int32_t n_freq, size_t *bytes);
+/* Eq. (2): d_gloc(s, n, i) = [(i w_n + mu) 1 - hop - diag(eps_s) -
+ * diag(sigma_s(i w_n))]^-1_ii.  d_eps: 2 x n_sites; d_sigma, d_gloc:
+ * spin-frequency-site.  Needs Im sigma(i w_n) < w_n (true of a causal
+ * self-energy), which keeps every eliminated block invertible. */
+hfqmc_status hfqmc_lattice_green(hfqmc_ctx *ctx, hfqmc_lattice *lat, int32_t n_freq, double beta, double mu,
+                                 const double *d_eps, const double *d_sigma, double *d_gloc, void *d_ws,
+                                 size_t ws_bytes);
+/* Weiss functions of the n_sel sites listed in `sites` (host, indices
+ * checked): W = (G_loc^-1 + sigma)^-1 into d_weiss_iw ([s][n][j], complex),
+ * and the solver's samples g(tau_l) = -W(tau_l), tau_l = l beta / L, l < L,
+ * into d_weiss_tau ([j][s][l]): the level 1 / (i w - e), e = eps_s,i - mu,
+ * transformed exactly, the rest summed over the n_freq frequencies and their
+ * negatives.  2 <= L <= 160.  The site list is copied into a buffer of the
+ * lattice, grown with hipMalloc when a longer list arrives. */
+hfqmc_status hfqmc_lattice_weiss(hfqmc_ctx *ctx, hfqmc_lattice *lat, int32_t n_freq, double beta, double mu,
+                                 int32_t L, const double *d_eps, const double *d_gloc, const double *d_sigma,
+                                 const int32_t *sites, int32_t n_sel, double *d_weiss_iw, double *d_weiss_tau);
+/* New self-energy of the listed sites (distinct; host list) from the solver's
+ * g(tau_k), k = 0 .. L, in d_gimp_tau ([j][s][k]) and densities d_density
+ * ([j][s]), given the Weiss functions d_weiss_iw of hfqmc_lattice_weiss:
+ * with sigma_inf = U (n_other spin - 1/2) and W_H = (W^-1 - sigma_inf)^-1,
+ * G_imp = W_H - int exp(i w tau) (g - g_H) dtau over the piecewise-linear
+ * interpolant, sigma_new = W^-1 - G_imp^-1 for n < max(1, L / 4), and
+ * sigma_inf + U^2 n_other (1 - n_other) / (i w_n) above.  Then
+ * sigma <- mix sigma_new + (1 - mix) sigma (0 < mix <= 1) at those sites;
+ * other sites keep theirs. */
+hfqmc_status hfqmc_lattice_sigma(hfqmc_ctx *ctx, hfqmc_lattice *lat, int32_t n_freq, double beta, double mu,
+                                 double U, int32_t L, const double *d_eps, const int32_t *sites, int32_t n_sel,
+                                 const double *d_weiss_iw, const double *d_gimp_tau, const double *d_density,
+                                 double mix, double *d_sigma);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhfqmc.so")
-SOURCES = ["hfqmc_sweep.hip", "hfqmc_sweep_global.hip", "hfqmc_abi.cpp"]
+SOURCES = ["hfqmc_sweep.hip", "hfqmc_sweep_global.hip", "hfqmc_lattice.hip", "hfqmc_abi.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -41,6 +41,10 @@ hipError_t kernel_occupancy(const KernelInfo* k, int* blocks_per_cu);
 hipError_t launch_sweep(const KernelInfo* k, int grid, hipStream_t st, const ImpDesc* descs, const int32_t* order,
                         int n_items, int* queue, uint8_t* ws);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+size_t lattice_work_bytes(int layer, int n_layers, int n_freq);
+hipError_t launch_lattice_green(const LatDesc& d, hipStream_t st);
+hipError_t launch_weiss(const WeissDesc& d, hipStream_t st);
+hipError_t launch_sigma(const SigmaDesc& d, hipStream_t st);
 }  // namespace hfqmc
 
 using namespace hfqmc;
@@ -1720,6 +1724,194 @@ hfqmc_status hfqmc_serve_stats(hfqmc_ctx* c, hfqmc_serve_stats_t* out) {
   out->active = (int32_t)S.ready.size() + inflight;
   out->capacity_used = S.used;
   out->capacity = S.capacity > 0 ? S.capacity : (double)c->n_cu;
+  return HFQMC_OK;
+}
+
+// ---------------------------------------------------------------- lattice
+
+}  // extern "C"
+
+struct hfqmc_lattice {
+  int n_sites = 0, layer = 0, n_layers = 0;
+  int device = 0;
+  double* d_hop = nullptr;     // n_layers blocks layer x layer, then (n_layers - 1) x layer couplings
+  int32_t* d_sites = nullptr;  // site list of the last Weiss / self-energy call
+  int sites_cap = 0;
+};
+
+namespace {
+
+// Copy a host site list into the lattice's device buffer (grown on demand),
+// after checking every index.
+hfqmc_status lattice_sites(hfqmc_ctx* c, hfqmc_lattice* lat, const int32_t* sites, int32_t n_sel) {
+  for (int j = 0; j < n_sel; ++j)
+    if (sites[j] < 0 || sites[j] >= lat->n_sites)
+      return fail(HFQMC_EINVAL, "site %d of the list (%d) outside [0,%d)", j, sites[j], lat->n_sites);
+  if (n_sel > lat->sites_cap) {
+    HIP_TRY(hipStreamSynchronize(c->stream));  // earlier calls may still read the old list
+    if (lat->d_sites) HIP_TRY(hipFree(lat->d_sites));
+    lat->d_sites = nullptr;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&lat->d_sites), sizeof(int32_t) * n_sel));
+    lat->sites_cap = n_sel;
+  }
+  HIP_TRY(hipMemcpyAsync(lat->d_sites, sites, sizeof(int32_t) * n_sel, hipMemcpyHostToDevice, c->stream));
+  return HFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, const double* hop,
+                                  hfqmc_lattice** out) {
+  if (!c || !hop || !out || layer < 1 || layer > kMaxLayer || n_sites < layer || n_sites % layer)
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_create: need 1 <= layer <= %d dividing n_sites", kMaxLayer);
+  const int N = n_sites, b = layer, nl = N / b;
+  double scale = 0.0;
+  for (size_t k = 0; k < (size_t)N * N; ++k) {
+    if (!std::isfinite(hop[k])) return fail(HFQMC_EINVAL, "hop[%zu] not finite", k);
+    scale = std::max(scale, std::fabs(hop[k]));
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const double h = hop[(size_t)i * N + j];
+      if (std::fabs(h - hop[(size_t)j * N + i]) > 1e-14 * scale)
+        return fail(HFQMC_EINVAL, "hop not symmetric at (%d,%d)", i, j);
+      const int li = i / b, lj = j / b;
+      const bool allowed = li == lj || (std::abs(li - lj) == 1 && i % b == j % b);
+      if (h != 0.0 && !allowed)
+        return fail(HFQMC_EINVAL,
+                    "hop(%d,%d) = %g: only hopping inside a layer of %d sites or between the same position of "
+                    "neighbouring layers is supported", i, j, h, b);
+    }
+  std::vector<double> img((size_t)nl * b * b + (size_t)(nl > 1 ? nl - 1 : 0) * b);
+  for (int k = 0; k < nl; ++k)
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) img[((size_t)k * b + i) * b + j] = hop[(size_t)(k * b + i) * N + k * b + j];
+  for (int k = 0; k + 1 < nl; ++k)
+    for (int j = 0; j < b; ++j) img[(size_t)nl * b * b + (size_t)k * b + j] = hop[(size_t)(k * b + j) * N + (k + 1) * b + j];
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  hfqmc_lattice* lat = new (std::nothrow) hfqmc_lattice;
+  if (!lat) return fail(HFQMC_ENOMEM, "out of host memory");
+  lat->n_sites = N;
+  lat->layer = b;
+  lat->n_layers = nl;
+  lat->device = c->device;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&lat->d_hop), sizeof(double) * img.size());
+  if (e == hipSuccess) e = hipMemcpy(lat->d_hop, img.data(), sizeof(double) * img.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (lat->d_hop) (void)hipFree(lat->d_hop);
+    delete lat;
+    return fail(HFQMC_EDEVICE, "hfqmc_lattice_create: %s", hipGetErrorString(e));
+  }
+  *out = lat;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx* c, hfqmc_lattice* lat) {
+  if (!c || !lat) return fail(HFQMC_EINVAL, "hfqmc_lattice_destroy: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  (void)hipFree(lat->d_hop);
+  if (lat->d_sites) (void)hipFree(lat->d_sites);
+  delete lat;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_workspace(const hfqmc_lattice* lat, int32_t n_freq, size_t* bytes) {
+  if (!lat || !bytes || n_freq < 1 || n_freq > kMaxFreq)
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_workspace: need 1 <= n_freq <= %d", kMaxFreq);
+  *bytes = lattice_work_bytes(lat->layer, lat->n_layers, n_freq);
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_green(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_freq, double beta, double mu,
+                                 const double* d_eps, const double* d_sigma, double* d_gloc, void* d_ws,
+                                 size_t ws_bytes) {
+  if (!c || !lat || !d_eps || !d_sigma || !d_gloc || !d_ws || n_freq < 1 || n_freq > kMaxFreq || !(beta > 0) ||
+      !std::isfinite(beta) || !std::isfinite(mu))
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_green: bad arguments");
+  const size_t need = lattice_work_bytes(lat->layer, lat->n_layers, n_freq);
+  if (ws_bytes < need) return fail(HFQMC_ENOMEM, "lattice workspace %zu bytes < %zu needed", ws_bytes, need);
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  LatDesc d{};
+  d.n_sites = lat->n_sites;
+  d.layer = lat->layer;
+  d.n_layers = lat->n_layers;
+  d.n_freq = n_freq;
+  d.beta = beta;
+  d.mu = mu;
+  d.blocks = lat->d_hop;
+  d.coupling = lat->d_hop + (size_t)lat->n_layers * lat->layer * lat->layer;
+  d.eps = d_eps;
+  d.sigma = d_sigma;
+  d.gloc = d_gloc;
+  d.work = reinterpret_cast<double*>(d_ws);
+  HIP_TRY(launch_lattice_green(d, c->stream));
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_weiss(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_freq, double beta, double mu, int32_t L,
+                                 const double* d_eps, const double* d_gloc, const double* d_sigma,
+                                 const int32_t* sites, int32_t n_sel, double* d_weiss_iw, double* d_weiss_tau) {
+  if (!c || !lat || !d_eps || !d_gloc || !d_sigma || !sites || !d_weiss_iw || !d_weiss_tau || n_sel < 1 ||
+      n_freq < 1 || n_freq > kMaxFreq || L < 2 || L > kMaxL || !(beta > 0) || !std::isfinite(beta) ||
+      !std::isfinite(mu))
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_weiss: bad arguments");
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  TRY(lattice_sites(c, lat, sites, n_sel));
+  WeissDesc d{};
+  d.n_sites = lat->n_sites;
+  d.n_freq = n_freq;
+  d.L = L;
+  d.n_sel = n_sel;
+  d.beta = beta;
+  d.mu = mu;
+  d.eps = d_eps;
+  d.gloc = d_gloc;
+  d.sigma = d_sigma;
+  d.sites = lat->d_sites;
+  d.weiss_iw = d_weiss_iw;
+  d.weiss_tau = d_weiss_tau;
+  HIP_TRY(launch_weiss(d, c->stream));
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_sigma(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_freq, double beta, double mu, double U,
+                                 int32_t L, const double* d_eps, const int32_t* sites, int32_t n_sel,
+                                 const double* d_weiss_iw, const double* d_gimp_tau, const double* d_density,
+                                 double mix, double* d_sigma) {
+  if (!c || !lat || !d_eps || !sites || !d_weiss_iw || !d_gimp_tau || !d_density || !d_sigma || n_sel < 1 ||
+      n_freq < 1 || n_freq > kMaxFreq || L < 2 || L > kMaxL || !(beta > 0) || !std::isfinite(beta) ||
+      !std::isfinite(mu) || !(U >= 0) || !std::isfinite(U) || !(mix > 0 && mix <= 1))
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_sigma: bad arguments");
+  std::vector<int32_t> sorted(sites, sites + n_sel);
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_sigma: a site appears twice in the list");
+  std::lock_guard<std::mutex> g(c->mu);
+  TRY(set_device(c));
+  TRY(lattice_sites(c, lat, sites, n_sel));
+  SigmaDesc d{};
+  d.n_sites = lat->n_sites;
+  d.n_freq = n_freq;
+  d.L = L;
+  d.n_sel = n_sel;
+  d.beta = beta;
+  d.mu = mu;
+  d.U = U;
+  d.mix = mix;
+  d.eps = d_eps;
+  d.sites = lat->d_sites;
+  d.weiss_iw = d_weiss_iw;
+  d.gimp_tau = d_gimp_tau;
+  d.density = d_density;
+  d.sigma = d_sigma;
+  HIP_TRY(launch_sigma(d, c->stream));
   return HFQMC_OK;
 }
 

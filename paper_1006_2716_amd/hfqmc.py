@@ -99,6 +99,14 @@ def lib():
             "hfqmc_poll": [_VP, C.c_uint64, C.POINTER(Result)],
             "hfqmc_cancel": [_VP, C.c_uint64],
             "hfqmc_serve_stats": [_VP, C.POINTER(ServeStats)],
+            "hfqmc_lattice_create": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(_VP)],
+            "hfqmc_lattice_destroy": [_VP, _VP],
+            "hfqmc_lattice_workspace": [_VP, C.c_int32, C.POINTER(C.c_size_t)],
+            "hfqmc_lattice_green": [_VP, _VP, C.c_int32, C.c_double, C.c_double, _VP, _VP, _VP, _VP, C.c_size_t],
+            "hfqmc_lattice_weiss": [_VP, _VP, C.c_int32, C.c_double, C.c_double, C.c_int32, _VP, _VP, _VP,
+                                    C.POINTER(C.c_int32), C.c_int32, _VP, _VP],
+            "hfqmc_lattice_sigma": [_VP, _VP, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, _VP,
+                                    C.POINTER(C.c_int32), C.c_int32, _VP, _VP, _VP, C.c_double, _VP],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -395,3 +403,88 @@ class Site:
         d = C.c_double()
         _check(lib().hfqmc_site_recompute(self.ctx.h, self.h, C.byref(d)), "hfqmc_site_recompute")
         return d.value
+
+
+# ---------------------------------------------------------------- lattice
+def _dev(t, dtype, shape, what):
+    """Check a torch tensor argument: CUDA, contiguous, dtype and shape."""
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{what}: need a contiguous {dtype} CUDA tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return _VP(t.data_ptr())
+
+
+class Lattice:
+    """Layered lattice for the self-consistency calls (hopping blocks on the
+    device).  Arrays are torch tensors on the context's device: eps float64
+    (2, N), sigma / gloc complex128 (2, n_freq, N)."""
+
+    def __init__(self, ctx: Context, hop, layer: int):
+        hop = np.ascontiguousarray(hop, dtype=np.float64)
+        self.ctx = ctx
+        self.n_sites = hop.shape[0]
+        self.layer = int(layer)
+        h = _VP()
+        _check(lib().hfqmc_lattice_create(ctx.h, self.n_sites, self.layer, _dp(hop), C.byref(h)),
+               "hfqmc_lattice_create")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if self.h:
+            _check(lib().hfqmc_lattice_destroy(self.ctx.h, self.h), "hfqmc_lattice_destroy")
+            self.h = None
+
+    def workspace_size(self, n_freq: int) -> int:
+        b = C.c_size_t()
+        _check(lib().hfqmc_lattice_workspace(self.h, n_freq, C.byref(b)), "hfqmc_lattice_workspace")
+        return b.value
+
+    def green(self, n_freq: int, beta: float, mu: float, eps, sigma, out=None):
+        """Eq. (2): site-diagonal lattice Green function, complex128 (2, n_freq, N)."""
+        torch = _torch()
+        N = self.n_sites
+        if out is None:
+            out = torch.empty((2, n_freq, N), dtype=torch.complex128, device=sigma.device)
+        need = self.workspace_size(n_freq)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=sigma.device)
+        _check(lib().hfqmc_lattice_green(self.ctx.h, self.h, n_freq, beta, mu,
+                                         _dev(eps, torch.float64, (2, N), "eps"),
+                                         _dev(sigma, torch.complex128, (2, n_freq, N), "sigma"),
+                                         _dev(out, torch.complex128, (2, n_freq, N), "gloc"),
+                                         _VP(self._ws.data_ptr()), self._ws.numel()), "hfqmc_lattice_green")
+        return out
+
+    def weiss(self, n_freq: int, beta: float, mu: float, L: int, eps, gloc, sigma, sites):
+        """Weiss functions of `sites`: (complex128 (2, n_freq, n_sel), float64 (n_sel, 2, L))."""
+        torch = _torch()
+        N = self.n_sites
+        st = np.ascontiguousarray(sites, dtype=np.int32)
+        n_sel = st.size
+        w_iw = torch.empty((2, n_freq, n_sel), dtype=torch.complex128, device=gloc.device)
+        w_tau = torch.empty((n_sel, 2, L), dtype=torch.float64, device=gloc.device)
+        _check(lib().hfqmc_lattice_weiss(self.ctx.h, self.h, n_freq, beta, mu, L,
+                                         _dev(eps, torch.float64, (2, N), "eps"),
+                                         _dev(gloc, torch.complex128, (2, n_freq, N), "gloc"),
+                                         _dev(sigma, torch.complex128, (2, n_freq, N), "sigma"),
+                                         st.ctypes.data_as(C.POINTER(C.c_int32)), n_sel,
+                                         _VP(w_iw.data_ptr()), _VP(w_tau.data_ptr())), "hfqmc_lattice_weiss")
+        return w_iw, w_tau
+
+    def sigma_update(self, n_freq: int, beta: float, mu: float, U: float, L: int, eps, sites, weiss_iw,
+                     gimp_tau, density, mix: float, sigma):
+        """sigma <- mix sigma_new + (1 - mix) sigma at `sites` (in place)."""
+        torch = _torch()
+        N = self.n_sites
+        st = np.ascontiguousarray(sites, dtype=np.int32)
+        n_sel = st.size
+        _check(lib().hfqmc_lattice_sigma(self.ctx.h, self.h, n_freq, beta, mu, U, L,
+                                         _dev(eps, torch.float64, (2, N), "eps"),
+                                         st.ctypes.data_as(C.POINTER(C.c_int32)), n_sel,
+                                         _dev(weiss_iw, torch.complex128, (2, n_freq, n_sel), "weiss_iw"),
+                                         _dev(gimp_tau, torch.float64, (n_sel, 2, L + 1), "gimp_tau"),
+                                         _dev(density, torch.float64, (n_sel, 2), "density"), mix,
+                                         _dev(sigma, torch.complex128, (2, n_freq, N), "sigma")),
+               "hfqmc_lattice_sigma")
+        return sigma
