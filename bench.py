@@ -28,6 +28,9 @@ Other workloads (one JSON line each, --workload NAME or all):
   slab     41x41 trap (V0 = 0.02, U = 8, beta = 16, L = 80, ~1000 atoms,
            AF seed), 1281 sites, 1000 + 10000 sweeps; fp64 and fp32-product
            delayed updates (k = 16)
+  rdmft    one real-space DMFT iteration of the 21x21 trap: lattice Green
+           function at 500 Matsubara frequencies, Weiss functions, the
+           325-site solve, self-energy; the lattice part alone on 41x41
 """
 from __future__ import annotations
 
@@ -237,9 +240,70 @@ def bench_lattice(args, name):
           res["fp64"]["ms"], {"workload": desc, "n_impurities": len(probs), "proposals": props}, legs=res)
 
 
+def _lattice_flops(layer, n_layers):
+    """Algorithmic flops of one (spin, frequency) matrix of the layered lattice
+    Green function: a Gauss-Jordan inverse per layer (8 b^3) forward, two
+    complex b x b products per layer (16 b^3) backward."""
+    b3 = float(layer) ** 3
+    return 8.0 * b3 * n_layers + 16.0 * b3 * (n_layers - 1)
+
+
+def bench_rdmft(args):
+    """One RDMFT iteration of the 21 x 21 trap (lattice Green function at 500
+    frequencies, Weiss functions, the 325-site solve, self-energy), and the
+    lattice part alone on the 41 x 41 trap."""
+    import torch
+    from paper_1006_2716_amd import hfqmc, workloads
+    from paper_1006_2716_amd.rdmft import RDMFT
+    nf = 500
+    parts = {}
+    for name, n, V0, U, beta, L, mu_eff in (("21x21", 21, 0.05, 8.0, 10.0, 40, 0.0),
+                                            ("41x41", 41, 0.02, 8.0, 16.0, 80, workloads.C5_MU_EFF)):
+        hop, eps, sites = workloads.trapped_lattice(n, V0, beta, mu_eff, 0.1)
+        ctx = hfqmc.Context(0)
+        r = RDMFT(ctx, hop, n, eps, mu_eff, U, beta, L, n_freq=nf)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        r.weiss(sites)  # warm-up
+        torch.cuda.synchronize()
+        reps = max(1, args.steps)
+        green_ms, weiss_ms = 0.0, 0.0
+        for _ in range(reps):  # events on the context's stream (torch's current one)
+            ev[0].record()
+            r.lat.green(nf, beta, mu_eff, r.eps, r.sigma, out=r.gloc)
+            ev[1].record()
+            r.lat.weiss(nf, beta, mu_eff, L, r.eps, r.gloc, r.sigma, sites)
+            ev[2].record()
+            torch.cuda.synchronize()
+            green_ms += ev[0].elapsed_time(ev[1]) / reps
+            weiss_ms += ev[1].elapsed_time(ev[2]) / reps
+        flops = 2 * nf * _lattice_flops(n, n)
+        leg = dict(sites=n * n, solved_sites=int(len(sites)), n_freq=nf, lattice_green_ms=green_ms,
+                   weiss_ms=weiss_ms, lattice_tflops=flops / (green_ms * 1e-3) / 1e12,
+                   lattice_flops=flops)
+        if name == "21x21":
+            it = r.iterate(sites, n_warmup=1000, n_measure=10000, seed=2, timing=True)
+            props = int(sum(x["proposals"] for x in it["results"]))
+            leg.update(iteration_ms=sum(it["ms"].values()), steps_ms=it["ms"], proposals=props,
+                       atoms=float(it["density"].sum()))
+        parts[name] = leg
+        r.close()
+        ctx.close()
+    c2 = parts["21x21"]
+    it_ms = c2["iteration_ms"]
+    _line("RDMFT iteration, 21x21 trap: proposals/s of the whole iteration", c2["proposals"] / (it_ms * 1e-3),
+          "proposals/s", 1, 0, it_ms,
+          {"workload": "21x21 open trap V0=0.05, U=8, beta=10, L=40, AF seed h=0.1 in the site energies, "
+                       "lattice Green function at 500 Matsubara frequencies x 2 spins, Weiss functions of the "
+                       "325 sites with n>1e-3, their 1000+10000-sweep solve, self-energy update"},
+          lattice_roofline={"bound": "alu", "kernel": "hfqmc::rgf_kernel<32>",
+                            "achieved": round(c2["lattice_tflops"], 3), "peak": 78.6, "unit": "TFLOP/s",
+                            "frac": round(c2["lattice_tflops"] / 78.6, 4), "traffic": None},
+          parts=parts)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "all"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -270,13 +334,15 @@ def main():
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
     if args.workload != "headline":
-        names = ["uneven", "serving", "trapped", "slab"] if args.workload == "all" else [args.workload]
+        names = ["uneven", "serving", "trapped", "slab", "rdmft"] if args.workload == "all" else [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
             if n == "uneven":
                 bench_uneven(args)
             elif n == "serving":
                 bench_serving(args)
+            elif n == "rdmft":
+                bench_rdmft(args)
             else:
                 bench_lattice(args, n)
         return

@@ -123,6 +123,19 @@ def trapped_square(n, V0, U, beta, L, mu_eff, h, n_warmup, n_measure, seed, n_mi
     return probs, sites, coords
 
 
+def trapped_lattice(n, V0, beta, mu_eff, h, n_min=1e-3):
+    """Inputs of the lattice self-consistency for an open n x n trap, sites
+    numbered row by row (rows are the layers): hop (N, N), eps (2, N) (trap
+    potential -/+ the staggered seed field), and the sites with U = 0 density
+    n_up + n_dn > n_min at inverse temperature beta (the ones solved; the same
+    list as trapped_square)."""
+    Hu, Hd, coords = trapped_square_onebody(n, n, V0, mu_eff, h)
+    hop = Hu - np.diag(np.diag(Hu))
+    eps = np.stack([np.diag(Hu), np.diag(Hd)]) + mu_eff
+    dens = densities_from_onebody(Hu, beta) + densities_from_onebody(Hd, beta)
+    return hop, eps, np.nonzero(dens > n_min)[0].astype(np.int32)
+
+
 def trapped_21x21(n_warmup=1000, n_measure=10000, seed=2):
     """Trapped 2D cloud: 21x21, V0 = 0.05, U = 8, beta = 10, L = 40, mu = U/2, AF seed h = 0.1."""
     return trapped_square(21, 0.05, 8.0, 10.0, 40, 0.0, 0.1, n_warmup, n_measure, seed)[0]
