@@ -31,6 +31,8 @@ Other workloads (one JSON line each, --workload NAME or all):
   rdmft    one real-space DMFT iteration of the 21x21 trap: lattice Green
            function at 500 Matsubara frequencies, Weiss functions, the
            325-site solve, self-energy; the lattice part alone on 41x41
+  trotter  dtau -> 0: the 21x21 trap's sites at L = 32, 40, 50 in one batch,
+           fitted even in dtau
 """
 from __future__ import annotations
 
@@ -301,9 +303,35 @@ def bench_rdmft(args):
           parts=parts)
 
 
+def bench_trotter(args):
+    """dtau -> 0 for the 21 x 21 trap's 325 sites: L = 32, 40, 50 (dtau =
+    0.3125, 0.25, 0.2) in one uneven-L batch, 200 + 2000 sweeps, then the fit
+    even in dtau per site."""
+    from paper_1006_2716_amd import hfqmc, workloads
+    from paper_1006_2716_amd.trotter import solve_extrapolated
+    Ls = (32, 40, 50)
+    by_L = {L: workloads.trapped_square(21, 0.05, 8.0, 10.0, L, 0.0, 0.1, 200, 2000, seed=2)[0] for L in Ls}
+    props = sum((p["n_warmup"] + p["n_measure"]) * p["L"] for L in Ls for p in by_L[L])
+    ctx = hfqmc.Context(0)
+    solve_extrapolated(ctx, {L: v[:4] for L, v in by_L.items()})  # warm-up (kernel load)
+    t0 = time.perf_counter()
+    est, per_L = solve_extrapolated(ctx, by_L, order=1)
+    ms = (time.perf_counter() - t0) * 1e3
+    ctx.close()
+    atoms = {L: float(sum(r["n_up"] + r["n_dn"] for r in per_L[L])) for L in Ls}
+    atoms0 = float(sum(e["n_up"] + e["n_dn"] for e in est))
+    dmax = max(abs(e["docc"] - r["docc"]) for e, r in zip(est, per_L[40]))
+    _line("dtau->0 extrapolation, 21x21 trap (3 grids, one batch): proposals/s", props / (ms * 1e-3),
+          "proposals/s", 1, 0, ms,
+          {"workload": "21x21 trap V0=0.05, U=8, beta=10, AF seed, 325 sites, L in {32,40,50} in one uneven-L "
+                       "batch, 200+2000 sweeps, weighted fit c0 + c1 dtau^2 per site and observable",
+           "proposals": props},
+          atoms_by_L=atoms, atoms_extrapolated=atoms0, max_docc_shift_vs_L40=dmax)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "all"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "trotter", "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -334,7 +362,8 @@ def main():
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
     if args.workload != "headline":
-        names = ["uneven", "serving", "trapped", "slab", "rdmft"] if args.workload == "all" else [args.workload]
+        names = ["uneven", "serving", "trapped", "slab", "rdmft", "trotter"] if args.workload == "all" \
+            else [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
             if n == "uneven":
@@ -343,6 +372,8 @@ def main():
                 bench_serving(args)
             elif n == "rdmft":
                 bench_rdmft(args)
+            elif n == "trotter":
+                bench_trotter(args)
             else:
                 bench_lattice(args, n)
         return

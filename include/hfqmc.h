@@ -265,6 +265,19 @@ typedef struct {
 } hfqmc_serve_stats_t;
 hfqmc_status hfqmc_serve_stats(hfqmc_ctx *ctx, hfqmc_serve_stats_t *out);
 
+/* ---- dtau -> 0: removal of the discretisation error ----
+ * The discretised problem's observables are even in dtau (the paper removes
+ * the Trotter error by extrapolating dtau -> 0; see the sentence on the
+ * discretisation after Eq. (2)).  Weighted least-squares fit of
+ * value_i = sum_k coef_k dtau_i^(2k), k = 0 .. order (0 <= order <= 3), over
+ * n >= order + 1 runs (host arrays), weights 1 / err_i^2 (err may be NULL:
+ * unweighted).  coef_0 is the dtau -> 0 estimate.  coef_err (may be NULL)
+ * receives sqrt of the diagonal of (A^T W A)^-1, NaN without err.  Pure host
+ * arithmetic (Householder QR); EINVAL for dtau <= 0, non-finite input or too
+ * few distinct dtau. */
+hfqmc_status hfqmc_extrapolate(int32_t n, const double *dtau, const double *value, const double *err, int32_t order,
+                               double *coef, double *coef_err);
+
 /* ---- real-space DMFT self-consistency around the solver ----
  * The lattice Dyson equation, Eq. (2) (site-diagonal self-energy, one inverse
  * per Matsubara frequency and spin), the impurity Dyson equation linking the

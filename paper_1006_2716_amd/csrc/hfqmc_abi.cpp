@@ -1727,6 +1727,92 @@ hfqmc_status hfqmc_serve_stats(hfqmc_ctx* c, hfqmc_serve_stats_t* out) {
   return HFQMC_OK;
 }
 
+// ---------------------------------------------------------------- dtau -> 0
+
+// Weighted least squares for O(dtau) = sum_k c_k dtau^(2k), k <= order, by
+// Householder QR of the weighted design matrix; errors from (A^T W A)^-1 =
+// R^-1 R^-T.
+hfqmc_status hfqmc_extrapolate(int32_t n, const double* dtau, const double* value, const double* err, int32_t order,
+                               double* coef, double* coef_err) {
+  if (n < 1 || !dtau || !value || !coef || order < 0 || order > 3 || n < order + 1)
+    return fail(HFQMC_EINVAL, "hfqmc_extrapolate: need n >= order + 1, 0 <= order <= 3");
+  const int m = order + 1;
+  std::vector<double> A((size_t)n * m), y(n);
+  for (int i = 0; i < n; ++i) {
+    if (!(dtau[i] > 0) || !std::isfinite(dtau[i]) || !std::isfinite(value[i]))
+      return fail(HFQMC_EINVAL, "hfqmc_extrapolate: point %d not finite or dtau <= 0", i);
+    double w = 1.0;
+    if (err) {
+      if (!(err[i] > 0) || !std::isfinite(err[i])) return fail(HFQMC_EINVAL, "hfqmc_extrapolate: err[%d] <= 0", i);
+      w = 1.0 / err[i];
+    }
+    const double x = dtau[i] * dtau[i];
+    double p = 1.0;
+    for (int k = 0; k < m; ++k, p *= x) A[(size_t)i * m + k] = w * p;
+    y[i] = w * value[i];
+  }
+  // Householder: A = Q R, apply Q^T to y; a column whose remainder after the
+  // earlier reflections is rounding-sized relative to its own norm means too
+  // few distinct dtau for this order
+  std::vector<double> col(m, 0.0);
+  for (int k = 0; k < m; ++k)
+    for (int i = 0; i < n; ++i) col[k] = std::hypot(col[k], A[(size_t)i * m + k]);
+  for (int k = 0; k < m; ++k) {
+    double nrm = 0.0;
+    for (int i = k; i < n; ++i) nrm = std::hypot(nrm, A[(size_t)i * m + k]);
+    if (nrm == 0.0) return fail(HFQMC_EINVAL, "hfqmc_extrapolate: too few distinct dtau for order %d", order);
+    const double akk = A[(size_t)k * m + k];
+    const double alpha = akk > 0 ? -nrm : nrm;
+    std::vector<double> v(n, 0.0);
+    v[k] = akk - alpha;
+    for (int i = k + 1; i < n; ++i) v[i] = A[(size_t)i * m + k];
+    double vv = 0.0;
+    for (int i = k; i < n; ++i) vv += v[i] * v[i];
+    if (vv > 0.0) {
+      for (int j = k; j < m; ++j) {
+        double d = 0.0;
+        for (int i = k; i < n; ++i) d += v[i] * A[(size_t)i * m + j];
+        d = 2.0 * d / vv;
+        for (int i = k; i < n; ++i) A[(size_t)i * m + j] -= d * v[i];
+      }
+      double d = 0.0;
+      for (int i = k; i < n; ++i) d += v[i] * y[i];
+      d = 2.0 * d / vv;
+      for (int i = k; i < n; ++i) y[i] -= d * v[i];
+    }
+    if (std::fabs(A[(size_t)k * m + k]) <= 1e-10 * col[k])
+      return fail(HFQMC_EINVAL, "hfqmc_extrapolate: too few distinct dtau for order %d", order);
+  }
+  // back substitution R c = Q^T y
+  for (int k = m - 1; k >= 0; --k) {
+    double s = y[k];
+    for (int j = k + 1; j < m; ++j) s -= A[(size_t)k * m + j] * coef[j];
+    coef[k] = s / A[(size_t)k * m + k];
+  }
+  if (coef_err) {
+    if (!err) {
+      for (int k = 0; k < m; ++k) coef_err[k] = NAN;
+    } else {
+      // Rinv (upper triangular), covariance = Rinv Rinv^T
+      std::vector<double> Ri((size_t)m * m, 0.0);
+      for (int j = 0; j < m; ++j) {
+        Ri[(size_t)j * m + j] = 1.0 / A[(size_t)j * m + j];
+        for (int i = j - 1; i >= 0; --i) {
+          double s = 0.0;
+          for (int k = i + 1; k <= j; ++k) s += A[(size_t)i * m + k] * Ri[(size_t)k * m + j];
+          Ri[(size_t)i * m + j] = -s / A[(size_t)i * m + i];
+        }
+      }
+      for (int k = 0; k < m; ++k) {
+        double s = 0.0;
+        for (int j = k; j < m; ++j) s += Ri[(size_t)k * m + j] * Ri[(size_t)k * m + j];
+        coef_err[k] = std::sqrt(s);
+      }
+    }
+  }
+  return HFQMC_OK;
+}
+
 // ---------------------------------------------------------------- lattice
 
 }  // extern "C"

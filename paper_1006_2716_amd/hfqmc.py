@@ -99,6 +99,8 @@ def lib():
             "hfqmc_poll": [_VP, C.c_uint64, C.POINTER(Result)],
             "hfqmc_cancel": [_VP, C.c_uint64],
             "hfqmc_serve_stats": [_VP, C.POINTER(ServeStats)],
+            "hfqmc_extrapolate": [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "hfqmc_lattice_create": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(_VP)],
             "hfqmc_lattice_destroy": [_VP, _VP],
             "hfqmc_lattice_workspace": [_VP, C.c_int32, C.POINTER(C.c_size_t)],
@@ -403,6 +405,18 @@ class Site:
         d = C.c_double()
         _check(lib().hfqmc_site_recompute(self.ctx.h, self.h, C.byref(d)), "hfqmc_site_recompute")
         return d.value
+
+
+def extrapolate(dtau, value, err=None, order: int = 1):
+    """dtau -> 0 fit value = sum_k c_k dtau^(2k): (c, c_err or None)."""
+    d = np.ascontiguousarray(dtau, dtype=np.float64)
+    v = np.ascontiguousarray(value, dtype=np.float64)
+    e = None if err is None else np.ascontiguousarray(err, dtype=np.float64)
+    c = np.zeros(order + 1)
+    ce = np.zeros(order + 1)
+    _check(lib().hfqmc_extrapolate(d.size, _dp(d), _dp(v), None if e is None else _dp(e), order, _dp(c), _dp(ce)),
+           "hfqmc_extrapolate")
+    return c, (None if e is None else ce)
 
 
 # ---------------------------------------------------------------- lattice

@@ -76,3 +76,30 @@ def test_null_context_is_rejected():
     assert lib.hfqmc_workspace_size(None, None, 0, None) == hfqmc.EINVAL
     assert lib.hfqmc_run(None) == hfqmc.EINVAL
     assert lib.hfqmc_collect(None, None) == hfqmc.EINVAL
+
+
+def test_extrapolation_fit_matches_the_oracle():
+    """Host-only library arithmetic: the dtau -> 0 fit against the oracle's
+    least squares, weighted and unweighted, orders 0 .. 2."""
+    from oracle import trotter as tr
+    rng = np.random.default_rng(4)
+    d = np.array([0.25, 0.2, 0.1667, 0.125, 0.1])
+    y = 0.12 + 0.3 * d ** 2 - 0.5 * d ** 4 + rng.normal(scale=1e-3, size=d.size)
+    e = rng.uniform(5e-4, 2e-3, size=d.size)
+    for order in (0, 1, 2):
+        c, ce = hfqmc.extrapolate(d, y, e, order)
+        rc, rce = tr.fit(d, y, e, order)
+        assert np.allclose(c, rc, rtol=1e-10, atol=1e-13) and np.allclose(ce, rce, rtol=1e-10)
+        c, ce = hfqmc.extrapolate(d, y, None, order)
+        assert ce is None and np.allclose(c, tr.fit(d, y, None, order)[0], rtol=1e-10, atol=1e-13)
+
+
+def test_extrapolation_rejects_bad_input():
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.extrapolate([0.1, 0.1], [1.0, 1.1], None, 1)  # one distinct dtau
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.extrapolate([0.1, 0.2], [1.0, 1.1], None, 2)  # too few points
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.extrapolate([0.1, -0.2], [1.0, 1.1], None, 1)
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.extrapolate([0.1, 0.2], [1.0, 1.1], [0.1, 0.0], 1)
