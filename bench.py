@@ -33,6 +33,8 @@ Other workloads (one JSON line each, --workload NAME or all):
            325-site solve, self-energy; the lattice part alone on 41x41
   trotter  dtau -> 0: the 21x21 trap's sites at L = 32, 40, 50 in one batch,
            fitted even in dtau
+  thermo   entropy from dS/dmu = dN/dT: 13x13 trap, U = 10, converged RDMFT
+           at 37 chemical potentials x 2 temperatures
 """
 from __future__ import annotations
 
@@ -329,9 +331,45 @@ def bench_trotter(args):
           atoms_by_L=atoms, atoms_extrapolated=atoms0, max_docc_shift_vs_L40=dmax)
 
 
+def bench_thermo(args):
+    """Entropy from dS/dmu = dN/dT on a 13 x 13 trap (V0 = 0.25, U = 10,
+    dtau = 0.1, T = 1/(4.2) .. 1/(3.8)): converged RDMFT at 37 chemical
+    potentials and two temperatures, seeded with a staggered field; central
+    and average entropy per particle and the staggered magnetization."""
+    from paper_1006_2716_amd import hfqmc, workloads
+    from paper_1006_2716_amd.thermo import entropy_scan, staggered_magnetization
+    n, V0, U, dtau = 13, 0.25, 10.0, 0.1
+    Hu, Hd, coords = workloads.trapped_square_onebody(n, n, V0, 0.0, 0.1)
+    hop = Hu - np.diag(np.diag(Hu))
+    eps_seed = np.stack([np.diag(Hu), np.diag(Hd)])
+    eps = np.stack([0.5 * (eps_seed[0] + eps_seed[1])] * 2)  # the trap alone: the seed field cancels
+    mus = np.linspace(-9.0, 0.0, 37)
+    sites = np.arange(n * n, dtype=np.int32)
+    ctx = hfqmc.Context(0)
+    t0 = time.perf_counter()
+    r = entropy_scan(ctx, hop, n, eps, eps_seed, U, mus, 38, 42, dtau, sites, 100, 2000, seed=5, n_freq=500,
+                     tol=5e-3, max_iter=5, n_bins=16)
+    ms = (time.perf_counter() - t0) * 1e3
+    ctx.close()
+    c = n * n // 2
+    N = float(r["n_hi"][-1].sum() + r["n_lo"][-1].sum()) / 2.0
+    dens = 0.5 * (r["n_lo"][-1] + r["n_hi"][-1])
+    m = staggered_magnetization(dens, coords)
+    _line("entropy scan, 13x13 trap (37 mu x 2 T, converged RDMFT): proposals/s", r["proposals"] / (ms * 1e-3),
+          "proposals/s", 1, 0, ms,
+          {"workload": "13x13 open trap V0=0.25, U=10, dtau=0.1, L=38/42, mu-U/2 from -9 to 0 (37 points), "
+                       "staggered seed 0.1 in the first iteration, 100+2000 sweeps, <=5 iterations per point",
+           "proposals": r["proposals"], "rdmft_iterations": int(sum(r["iterations"]))},
+          T=r["T"], atoms=N, entropy_central=float(r["s"][-1][c]), entropy_central_err=float(r["s_err"][-1][c]),
+          entropy_per_particle=float(r["s"][-1].sum() / N),
+          entropy_per_particle_err=float(np.sqrt((r["s_err"][-1] ** 2).sum()) / N),
+          m_stag_central=float(m[c]), m_stag_max=float(np.abs(m).max()))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "trotter", "all"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "trotter", "thermo",
+                             "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -362,8 +400,8 @@ def main():
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
     if args.workload != "headline":
-        names = ["uneven", "serving", "trapped", "slab", "rdmft", "trotter"] if args.workload == "all" \
-            else [args.workload]
+        names = ["uneven", "serving", "trapped", "slab", "rdmft", "trotter", "thermo"] \
+            if args.workload == "all" else [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
             if n == "uneven":
@@ -374,6 +412,8 @@ def main():
                 bench_rdmft(args)
             elif n == "trotter":
                 bench_trotter(args)
+            elif n == "thermo":
+                bench_thermo(args)
             else:
                 bench_lattice(args, n)
         return

@@ -278,6 +278,18 @@ hfqmc_status hfqmc_serve_stats(hfqmc_ctx *ctx, hfqmc_serve_stats_t *out);
 hfqmc_status hfqmc_extrapolate(int32_t n, const double *dtau, const double *value, const double *err, int32_t order,
                                double *coef, double *coef_err);
 
+/* ---- entropy from dS/dmu = dN/dT ----
+ * Sampling gives no entropy directly; the paper integrates the temperature
+ * derivative of the densities over the chemical potential from the empty
+ * system (mu -> -inf, S = 0): see the entropy discussion after the
+ * magnetization results.  For every site i (host arrays, [k][i] layout):
+ * dn_i/dT at mu_k = (n_hi - n_lo) / (T_hi - T_lo) (central difference, for
+ * T = (T_lo + T_hi) / 2) and s[k][i] = trapezoid integral of it over
+ * mu_0 .. mu_k, the lowest grid point taken as empty (s = 0).  mu strictly
+ * ascending, n_mu >= 2, 0 < T_lo < T_hi.  Pure host arithmetic. */
+hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double *mu, const double *n_lo, const double *n_hi,
+                           double T_lo, double T_hi, double *s);
+
 /* ---- real-space DMFT self-consistency around the solver ----
  * The lattice Dyson equation, Eq. (2) (site-diagonal self-energy, one inverse
  * per Matsubara frequency and spin), the impurity Dyson equation linking the

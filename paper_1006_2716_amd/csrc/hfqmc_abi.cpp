@@ -1813,6 +1813,35 @@ hfqmc_status hfqmc_extrapolate(int32_t n, const double* dtau, const double* valu
   return HFQMC_OK;
 }
 
+// ---------------------------------------------------------------- entropy
+
+hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double* mu, const double* n_lo, const double* n_hi,
+                           double T_lo, double T_hi, double* s) {
+  if (n_mu < 2 || n_sites < 1 || !mu || !n_lo || !n_hi || !s || !(T_lo > 0) || !(T_hi > T_lo) ||
+      !std::isfinite(T_hi))
+    return fail(HFQMC_EINVAL, "hfqmc_entropy: need n_mu >= 2, n_sites >= 1, 0 < T_lo < T_hi");
+  for (int k = 0; k < n_mu; ++k) {
+    if (!std::isfinite(mu[k]) || (k > 0 && !(mu[k] > mu[k - 1])))
+      return fail(HFQMC_EINVAL, "hfqmc_entropy: mu must be finite and strictly ascending (index %d)", k);
+    for (int i = 0; i < n_sites; ++i)
+      if (!std::isfinite(n_lo[(size_t)k * n_sites + i]) || !std::isfinite(n_hi[(size_t)k * n_sites + i]))
+        return fail(HFQMC_EINVAL, "hfqmc_entropy: density (%d,%d) not finite", k, i);
+  }
+  const double inv = 1.0 / (T_hi - T_lo);
+  for (int i = 0; i < n_sites; ++i) {
+    double acc = 0.0;
+    double prev = (n_hi[i] - n_lo[i]) * inv;
+    s[i] = 0.0;
+    for (int k = 1; k < n_mu; ++k) {
+      const double g = (n_hi[(size_t)k * n_sites + i] - n_lo[(size_t)k * n_sites + i]) * inv;
+      acc += (mu[k] - mu[k - 1]) * (g + prev) / 2.0;
+      s[(size_t)k * n_sites + i] = acc;
+      prev = g;
+    }
+  }
+  return HFQMC_OK;
+}
+
 // ---------------------------------------------------------------- lattice
 
 }  // extern "C"

@@ -101,6 +101,8 @@ def lib():
             "hfqmc_serve_stats": [_VP, C.POINTER(ServeStats)],
             "hfqmc_extrapolate": [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+            "hfqmc_entropy": [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.c_double, C.c_double, C.POINTER(C.c_double)],
             "hfqmc_lattice_create": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(_VP)],
             "hfqmc_lattice_destroy": [_VP, _VP],
             "hfqmc_lattice_workspace": [_VP, C.c_int32, C.POINTER(C.c_size_t)],
@@ -417,6 +419,19 @@ def extrapolate(dtau, value, err=None, order: int = 1):
     _check(lib().hfqmc_extrapolate(d.size, _dp(d), _dp(v), None if e is None else _dp(e), order, _dp(c), _dp(ce)),
            "hfqmc_extrapolate")
     return c, (None if e is None else ce)
+
+
+def entropy(mu, n_lo, n_hi, T_lo: float, T_hi: float):
+    """Per-site entropy s[k, i] from densities n_lo, n_hi (K, sites) at T_lo < T_hi
+    on the ascending grid mu (K,), integrated from the empty system at mu[0]."""
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    a = np.ascontiguousarray(n_lo, dtype=np.float64)
+    b = np.ascontiguousarray(n_hi, dtype=np.float64)
+    if a.ndim != 2 or a.shape != b.shape or a.shape[0] != m.size:
+        raise ValueError("entropy: need n_lo, n_hi of shape (len(mu), n_sites)")
+    out = np.zeros_like(a)
+    _check(lib().hfqmc_entropy(m.size, a.shape[1], _dp(m), _dp(a), _dp(b), T_lo, T_hi, _dp(out)), "hfqmc_entropy")
+    return out
 
 
 # ---------------------------------------------------------------- lattice

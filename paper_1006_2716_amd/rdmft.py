@@ -26,11 +26,12 @@ class RDMFT:
     of the Hartree-shifted levels (mu - U/2), sigma relative to them."""
 
     def __init__(self, ctx: hfqmc.Context, hop, layer: int, eps, mu: float, U: float, beta: float, L: int,
-                 n_freq: int = 500, mix: float = 1.0, sigma0=None):
+                 n_freq: int = 500, mix: float = 1.0, sigma0=None, lattice: hfqmc.Lattice | None = None):
         torch = _torch()
         self.ctx = ctx
         self.dev = f"cuda:{ctx.device}"
-        self.lat = hfqmc.Lattice(ctx, hop, layer)
+        self.own_lattice = lattice is None
+        self.lat = hfqmc.Lattice(ctx, hop, layer) if lattice is None else lattice
         self.N = self.lat.n_sites
         self.eps = torch.as_tensor(np.asarray(eps, dtype=np.float64), device=self.dev).contiguous()
         self.mu, self.U, self.beta, self.L, self.n_freq, self.mix = float(mu), float(U), float(beta), int(L), \
@@ -42,7 +43,12 @@ class RDMFT:
         self.gloc = None
 
     def close(self):
-        self.lat.close()
+        if self.own_lattice:
+            self.lat.close()
+
+    def set_eps(self, eps):
+        """New site energies (e.g. the seed field switched off after the first iteration)."""
+        self.eps = _torch().as_tensor(np.asarray(eps, dtype=np.float64), device=self.dev).contiguous()
 
     def weiss(self, sites):
         """Lattice Green function and Weiss functions of `sites` from the
@@ -72,22 +78,62 @@ class RDMFT:
 
     def iterate(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
                 sweep_offset=0, timing=False):
-        """One full iteration; returns the solver results, the densities and
-        (timing=True) the wall time of each step in ms."""
+        """One full iteration; returns the solver results (solved sites), the
+        densities of all listed sites and (timing=True) the wall time of each
+        step in ms.  A site whose Weiss function is empty or full to rounding
+        (g(0+) within 1e-12 of 0 or 1, far below or above the band) is not
+        solved: its density is the Weiss function's and its self-energy stays."""
         torch = _torch()
+        sites = np.asarray(sites, dtype=np.int32)
         sync = (lambda: torch.cuda.synchronize(self.dev)) if timing else (lambda: None)
         t = [time.perf_counter()]
         w_iw, w_tau = self.weiss(sites)
         sync()
         t.append(time.perf_counter())
-        res = self.ctx.solve(self.problems(sites, w_tau, n_warmup, n_measure, seed, n_bins, recompute_every,
-                                           n_chains, sweep_offset))
-        t.append(time.perf_counter())
-        dens = self.update(sites, w_iw, res)
+        g0 = w_tau[:, :, 0]
+        live = np.all((g0 > 1e-12) & (g0 < 1.0 - 1e-12), axis=1)
+        dens = 1.0 - g0.copy()
+        dens_err = np.zeros_like(dens)
+        total_err = np.zeros(len(sites))  # error of n_up + n_dn from the bins (the spins are correlated)
+        res = []
+        if live.any():
+            idx = np.nonzero(live)[0]
+            res = self.ctx.solve(self.problems(sites[idx], w_tau[idx], n_warmup, n_measure, seed, n_bins,
+                                               recompute_every, n_chains, sweep_offset))
+            t.append(time.perf_counter())
+            sub = w_iw if live.all() else w_iw[:, :, torch.as_tensor(idx, device=self.dev)].contiguous()
+            dens[idx] = self.update(sites[idx], sub, res)
+            dens_err[idx] = np.array([[x["n_up_err"], x["n_dn_err"]] for x in res])
+            L = self.L
+            for j, x in zip(idx, res):
+                tot = x["bins"][:, 2 * L + 2] + x["bins"][:, 2 * L + 3]
+                total_err[j] = tot.std(ddof=1) / np.sqrt(tot.size)
+        else:
+            t.append(time.perf_counter())
         sync()
         t.append(time.perf_counter())
-        out = dict(results=res, density=dens, weiss_tau=w_tau)
+        out = dict(results=res, density=dens, density_err=dens_err, total_err=total_err, weiss_tau=w_tau,
+                   solved=live)
         if timing:
             out["ms"] = dict(lattice_and_weiss=1e3 * (t[1] - t[0]), solve=1e3 * (t[2] - t[1]),
                              sigma=1e3 * (t[3] - t[2]))
+        return out
+
+    def converge(self, sites, n_warmup, n_measure, seed, tol=2e-3, max_iter=20, eps_after=None, **kw):
+        """Iterate until the largest density change between iterations is below
+        tol (or max_iter).  eps_after (e.g. without the seed field) replaces
+        the site energies after the first iteration.  Returns the last
+        iteration's output with 'history' (density change per iteration)."""
+        prev, hist = None, []
+        for it in range(max_iter):
+            out = self.iterate(sites, n_warmup, n_measure, seed + it, **kw)
+            if it == 0 and eps_after is not None:
+                self.set_eps(eps_after)
+            d = out["density"]
+            if prev is not None:
+                hist.append(float(np.max(np.abs(d - prev))))
+                if hist[-1] < tol:
+                    break
+            prev = d
+        out["history"] = hist
         return out

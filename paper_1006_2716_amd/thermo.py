@@ -1,0 +1,89 @@
+"""Thermodynamics from converged real-space DMFT solutions: density scans over
+the chemical potential at two temperatures, the entropy from
+dS/dmu = dN/dT (hfqmc_entropy), and staggered-magnetization profiles.
+
+Temperatures are set through beta = L * dtau at a fixed dtau, so both
+temperatures of a derivative carry the same discretisation error.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import hfqmc
+from .rdmft import RDMFT
+
+
+def staggered_magnetization(density, coords):
+    """(-1)^(x + y) (n_up - n_dn) per site: density (sites, 2), coords (sites, 2)."""
+    c = np.asarray(coords)
+    d = np.asarray(density)
+    return np.where(c.sum(axis=1) % 2 == 0, 1.0, -1.0) * (d[:, 0] - d[:, 1])
+
+
+def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, L, dtau, sites, n_warmup, n_measure, seed,
+                 n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True):
+    """Converged densities (len(mus), len(sites), 2) at beta = L dtau for every
+    chemical potential (Hartree-shifted, ascending), the self-energy carried
+    from one mu to the next; eps_seed (with a seed field) is used for the first
+    iteration at the first mu, eps afterwards.  Also returns the errors of
+    n_up + n_dn (len(mus), len(sites)), the iteration counts and the solver
+    proposals."""
+    beta = L * dtau
+    out = np.zeros((len(mus), len(sites), 2))
+    err = np.zeros((len(mus), len(sites)))  # of n_up + n_dn
+    iters, props = [], 0
+    sigma = None
+    for k, mu in enumerate(mus):
+        first = k == 0 or not warm_start
+        r = RDMFT(ctx, hop, layer, eps_seed if first else eps, mu, U, beta, L, n_freq=n_freq,
+                  sigma0=None if first else sigma, lattice=lattice)
+        res = r.converge(sites, n_warmup, n_measure, seed + 1000 * k, tol=tol, max_iter=max_iter,
+                         eps_after=eps if first else None, n_bins=n_bins)
+        out[k] = res["density"]
+        err[k] = res["total_err"]
+        iters.append(len(res["history"]) + 1)
+        props += int(sum(x["proposals"] for x in res["results"]))
+        sigma = r.sigma.cpu().numpy()
+        r.close()
+    return out, err, iters, props
+
+
+def entropy_error(mus, err_lo, err_hi, T_lo, T_hi):
+    """Statistical error of each site's entropy from the densities' errors
+    (independent runs at the two temperatures and at every mu), propagated
+    through the central difference and the trapezoid weights: (K, sites)."""
+    mus = np.asarray(mus, dtype=np.float64)
+    var = (np.asarray(err_lo) ** 2 + np.asarray(err_hi) ** 2) / (T_hi - T_lo) ** 2
+    h = np.diff(mus)
+    out = np.zeros_like(var)
+    acc = np.zeros(var.shape[1])
+    for k in range(1, len(mus)):
+        # s_k = sum_j w_j g_j with w_0 = h_0/2, w_j = (h_j-1 + h_j)/2, w_k = h_k-1/2
+        w = np.zeros(k + 1)
+        w[:k] += 0.5 * h[:k]
+        w[1:k + 1] += 0.5 * h[:k]
+        acc = (w[:, None] ** 2 * var[:k + 1]).sum(axis=0)
+        out[k] = np.sqrt(acc)
+    return out
+
+
+def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites, n_warmup, n_measure, seed,
+                 **kw):
+    """Per-site entropy at the temperature between T_hi = 1/(L_lo dtau) and
+    T_lo = 1/(L_hi dtau) on the grid mus (the first point taken as empty).
+    Returns dict(s (len(mus), sites), s_err (statistical, from the last
+    iteration's bins at every point), n_lo, n_hi, T_lo, T_hi, T, iterations,
+    proposals)."""
+    lat = hfqmc.Lattice(ctx, hop, layer)
+    try:
+        n_lo, e_lo, it_lo, p_lo = density_scan(ctx, lat, hop, layer, eps, eps_seed, U, mus, L_hi, dtau, sites,
+                                               n_warmup, n_measure, seed, **kw)
+        n_hi, e_hi, it_hi, p_hi = density_scan(ctx, lat, hop, layer, eps, eps_seed, U, mus, L_lo, dtau, sites,
+                                               n_warmup, n_measure, seed + 7, **kw)
+    finally:
+        lat.close()
+    T_lo, T_hi = 1.0 / (L_hi * dtau), 1.0 / (L_lo * dtau)
+    s = hfqmc.entropy(mus, n_lo.sum(axis=2), n_hi.sum(axis=2), T_lo, T_hi)
+    s_err = entropy_error(mus, e_lo, e_hi, T_lo, T_hi)
+    return dict(s=s, s_err=s_err, n_lo=n_lo, n_hi=n_hi, T_lo=T_lo, T_hi=T_hi, T=0.5 * (T_lo + T_hi),
+                iterations=it_lo + it_hi, proposals=p_lo + p_hi)

@@ -103,3 +103,17 @@ def test_extrapolation_rejects_bad_input():
         hfqmc.extrapolate([0.1, -0.2], [1.0, 1.1], None, 1)
     with pytest.raises(hfqmc.HFQMCError):
         hfqmc.extrapolate([0.1, 0.2], [1.0, 1.1], [0.1, 0.0], 1)
+
+
+def test_entropy_integral_matches_the_oracle():
+    from oracle import thermo as th
+    rng = np.random.default_rng(8)
+    mu = np.sort(rng.uniform(-5, 2, size=40))
+    a = rng.uniform(0, 2, size=(40, 7))
+    b = a + rng.normal(scale=0.01, size=a.shape)
+    s = hfqmc.entropy(mu, a, b, 0.2, 0.22)
+    assert np.allclose(s, th.entropy_from_densities(mu, a, b, 0.2, 0.22), rtol=1e-12, atol=1e-14)
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.entropy(mu[::-1], a, b, 0.2, 0.22)
+    with pytest.raises(hfqmc.HFQMCError):
+        hfqmc.entropy(mu, a, b, 0.22, 0.2)

@@ -1,0 +1,72 @@
+"""Thermodynamics on converged self-consistent solutions (GPU, through the C
+ABI): the entropy from dS/dmu = dN/dT over a density scan reproduces the
+free-fermion entropy of a trapped lattice site by site, and the interacting
+loop converges to the particle-hole symmetric solution at half filling."""
+import numpy as np
+import pytest
+
+from paper_1006_2716_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1006_2716_amd import hfqmc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = hfqmc.Context(0)
+    yield c
+    c.close()
+
+
+def _lattice(n, V0, h=0.0):
+    Hu, Hd, coords = wl.trapped_square_onebody(n, n, V0, 0.0, h)
+    return Hu - np.diag(np.diag(Hu)), np.stack([np.diag(Hu), np.diag(Hd)]), coords
+
+
+def _s_of_f(f):
+    f = np.clip(f, 1e-300, 1 - 1e-16)
+    return -(f * np.log(f) + (1 - f) * np.log1p(-f))
+
+
+def test_entropy_scan_reproduces_free_fermions(ctx):
+    from paper_1006_2716_amd.thermo import entropy_scan
+    hop, eps, _ = _lattice(4, 0.3)
+    mus = np.linspace(-7.5, 1.0, 86)
+    sites = np.arange(16, dtype=np.int32)
+    print("entropy scan, 4x4 trap, U = 0, 86 chemical potentials x 2 temperatures", flush=True)
+    r = entropy_scan(ctx, hop, 4, eps, eps, 0.0, mus, 38, 42, 0.1, sites, 1, 4, seed=3, n_freq=500, max_iter=2,
+                     n_bins=2)
+    E, phi = np.linalg.eigh(hop + np.diag(eps[0]))
+    T = r["T"]
+    exact = np.stack([2 * (phi ** 2) @ _s_of_f(0.5 * (1 - np.tanh(0.5 * (E - m) / T))) for m in mus])
+    err = np.max(np.abs(r["s"] - exact))
+    print(f"T = {T:.5f}: max |s - s_exact| = {err:.2e}, total S = {r['s'][-1].sum():.4f}")
+    assert err < 3e-3
+
+
+def test_half_filling_is_particle_hole_symmetric(ctx):
+    """Open 4 x 4 lattice, no trap, mu = U/2 (0 after the Hartree shift),
+    U = 4, beta = 4: particle-hole symmetry combined with a spin flip
+    survives any antiferromagnetic order the loop develops, and in the
+    discrete problem n_up + n_dn = 1 holds configuration by configuration, so
+    every density is 1 and the real parts of the two spins' self-energies
+    (relative to the Hartree shift) cancel, to rounding."""
+    from paper_1006_2716_amd.rdmft import RDMFT
+    hop, eps, coords = _lattice(4, 0.0)
+    r = RDMFT(ctx, hop, 4, eps, 0.0, 4.0, 4.0, 16, n_freq=200)
+    try:
+        sites = np.arange(16, dtype=np.int32)
+        out = r.converge(sites, 200, 8000, seed=21, tol=0.01, max_iter=6, n_bins=16, n_chains=4)
+        n = out["density"].sum(axis=1)
+        err = np.array([np.hypot(x["n_up_err"], x["n_dn_err"]) for x in out["results"]])
+        z = (n - 1.0) / err
+        print(f"history {out['history']}, max |z| {np.abs(z).max():.2f}")
+        assert np.max(np.abs(n - 1.0)) < 1e-10 and np.abs(z).max() < 1e-6
+        sig = r.sigma.cpu().numpy()
+        re_sum = np.max(np.abs(sig[0].real + sig[1].real))
+        print(f"max |Re(sigma_up + sigma_dn)| {re_sum:.2e}, max |Im sigma| {np.max(np.abs(sig.imag)):.3f}")
+        assert re_sum < 1e-10
+    finally:
+        r.close()

@@ -54,3 +54,25 @@ def test_hubbard_atom():
 def test_staggered_sign_pattern():
     coords = np.array([(0, 0), (0, 1), (1, 1), (2, 1)])
     assert np.array_equal(th.staggered([1.0, 1.0, 1.0, 1.0], coords), [1.0, -1.0, 1.0, -1.0])
+
+
+def test_package_staggered_magnetization_matches_the_oracle():
+    from paper_1006_2716_amd.thermo import staggered_magnetization
+    rng = np.random.default_rng(2)
+    _, _, coords = wl.trapped_square_onebody(5, 5, 0.1, 0.0)
+    d = rng.uniform(0, 1, size=(25, 2))
+    assert np.array_equal(staggered_magnetization(d, coords), th.staggered(d[:, 0] - d[:, 1], coords))
+
+
+def test_entropy_error_propagation_matches_monte_carlo():
+    """The propagated error of the trapezoid integral against the spread of
+    the integral over many noisy copies of the same densities."""
+    from paper_1006_2716_amd.thermo import entropy_error
+    rng = np.random.default_rng(9)
+    mu = np.sort(rng.uniform(-3, 1, size=12))
+    n = rng.uniform(0, 1, size=(12, 3))
+    e_lo, e_hi = rng.uniform(1e-3, 3e-3, size=(2, 12, 3))
+    draws = [th.entropy_from_densities(mu, n + e_lo * rng.normal(size=n.shape), n + 0.01 + e_hi * rng.normal(
+        size=n.shape), 0.2, 0.21)[-1] for _ in range(4000)]
+    spread = np.std(draws, axis=0)
+    assert np.allclose(entropy_error(mu, e_lo, e_hi, 0.2, 0.21)[-1], spread, rtol=0.06)
