@@ -34,7 +34,7 @@ Other workloads (one JSON line each, --workload NAME or all):
   trotter  dtau -> 0: the 21x21 trap's sites at L = 32, 40, 50 in one batch,
            fitted even in dtau
   thermo   entropy from dS/dmu = dN/dT: 13x13 trap, U = 10, converged RDMFT
-           at 37 chemical potentials x 2 temperatures
+           at 45 chemical potentials x 2 temperatures
 """
 from __future__ import annotations
 
@@ -333,9 +333,11 @@ def bench_trotter(args):
 
 def bench_thermo(args):
     """Entropy from dS/dmu = dN/dT on a 13 x 13 trap (V0 = 0.25, U = 10,
-    dtau = 0.1, T = 1/(4.2) .. 1/(3.8)): converged RDMFT at 37 chemical
-    potentials and two temperatures, seeded with a staggered field; central
-    and average entropy per particle and the staggered magnetization."""
+    dtau = 0.1, T = 1/(4.2) .. 1/(3.8)): converged RDMFT at 45 chemical
+    potentials and two temperatures, from the empty system up to half filling
+    at the centre, seeded with a staggered field; central and average entropy
+    per particle (with their statistical errors) and the staggered
+    magnetization."""
     from paper_1006_2716_amd import hfqmc, workloads
     from paper_1006_2716_amd.thermo import entropy_scan, staggered_magnetization
     n, V0, U, dtau = 13, 0.25, 10.0, 0.1
@@ -343,7 +345,7 @@ def bench_thermo(args):
     hop = Hu - np.diag(np.diag(Hu))
     eps_seed = np.stack([np.diag(Hu), np.diag(Hd)])
     eps = np.stack([0.5 * (eps_seed[0] + eps_seed[1])] * 2)  # the trap alone: the seed field cancels
-    mus = np.linspace(-9.0, 0.0, 37)
+    mus = np.linspace(-11.0, 0.0, 45)
     sites = np.arange(n * n, dtype=np.int32)
     ctx = hfqmc.Context(0)
     t0 = time.perf_counter()
@@ -355,10 +357,11 @@ def bench_thermo(args):
     N = float(r["n_hi"][-1].sum() + r["n_lo"][-1].sum()) / 2.0
     dens = 0.5 * (r["n_lo"][-1] + r["n_hi"][-1])
     m = staggered_magnetization(dens, coords)
-    _line("entropy scan, 13x13 trap (37 mu x 2 T, converged RDMFT): proposals/s", r["proposals"] / (ms * 1e-3),
+    _line("entropy scan, 13x13 trap (45 mu x 2 T, converged RDMFT): proposals/s", r["proposals"] / (ms * 1e-3),
           "proposals/s", 1, 0, ms,
-          {"workload": "13x13 open trap V0=0.25, U=10, dtau=0.1, L=38/42, mu-U/2 from -9 to 0 (37 points), "
-                       "staggered seed 0.1 in the first iteration, 100+2000 sweeps, <=5 iterations per point",
+          {"workload": "13x13 open trap V0=0.25, U=10, dtau=0.1, L=38/42, mu-U/2 from -11 to 0 (45 points), "
+                       "staggered seed 0.1 in the first iteration at each point, 100+2000 sweeps, <=5 iterations "
+                       "per point",
            "proposals": r["proposals"], "rdmft_iterations": int(sum(r["iterations"]))},
           T=r["T"], atoms=N, entropy_central=float(r["s"][-1][c]), entropy_central_err=float(r["s_err"][-1][c]),
           entropy_per_particle=float(r["s"][-1].sum() / N),

@@ -23,22 +23,24 @@ def staggered_magnetization(density, coords):
 def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, L, dtau, sites, n_warmup, n_measure, seed,
                  n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True):
     """Converged densities (len(mus), len(sites), 2) at beta = L dtau for every
-    chemical potential (Hartree-shifted, ascending), the self-energy carried
-    from one mu to the next; eps_seed (with a seed field) is used for the first
-    iteration at the first mu, eps afterwards.  Also returns the errors of
-    n_up + n_dn (len(mus), len(sites)), the iteration counts and the solver
-    proposals."""
+    chemical potential (Hartree-shifted, ascending).  The scan starts from the
+    empty system, whose self-energy is zero, i.e. -U/2 relative to the
+    Hartree-shifted levels, and carries the self-energy from one mu to the
+    next; eps_seed (with a seed field) is used for the first iteration at
+    every mu, eps afterwards.  Also returns the errors of n_up + n_dn
+    (len(mus), len(sites)), the iteration counts and the solver proposals."""
     beta = L * dtau
     out = np.zeros((len(mus), len(sites), 2))
     err = np.zeros((len(mus), len(sites)))  # of n_up + n_dn
     iters, props = [], 0
-    sigma = None
+    N = lattice.n_sites
+    empty = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
+    sigma = empty
     for k, mu in enumerate(mus):
-        first = k == 0 or not warm_start
-        r = RDMFT(ctx, hop, layer, eps_seed if first else eps, mu, U, beta, L, n_freq=n_freq,
-                  sigma0=None if first else sigma, lattice=lattice)
-        res = r.converge(sites, n_warmup, n_measure, seed + 1000 * k, tol=tol, max_iter=max_iter,
-                         eps_after=eps if first else None, n_bins=n_bins)
+        r = RDMFT(ctx, hop, layer, eps_seed, mu, U, beta, L, n_freq=n_freq,
+                  sigma0=sigma if warm_start else empty, lattice=lattice)
+        res = r.converge(sites, n_warmup, n_measure, seed + 1000 * k, tol=tol, max_iter=max_iter, eps_after=eps,
+                         n_bins=n_bins)
         out[k] = res["density"]
         err[k] = res["total_err"]
         iters.append(len(res["history"]) + 1)
