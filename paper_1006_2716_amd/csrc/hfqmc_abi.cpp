@@ -30,6 +30,7 @@
 
 #include "hfqmc.h"
 #include "hfqmc_internal.h"
+#include "hfqmc_lattice.h"
 
 namespace hfqmc {
 struct KernelInfo;

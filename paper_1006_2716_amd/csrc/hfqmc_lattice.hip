@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include "hfqmc_internal.h"
+#include "hfqmc_lattice.h"
 
 namespace hfqmc {
 
