@@ -307,7 +307,7 @@ hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double *mu, cons
  * doubles; a "spin-frequency-site" array holds element (s, n, i) at
  * (s * n_freq + n) * n_sites + i.  Every array argument named d_* is device
  * memory owned by the caller; all calls are asynchronous on the context's
- * stream and allocate nothing except where stated.
+ * stream and allocate no device memory.
  *
  * Lattice structure.  Sites are numbered layer by layer (n_sites = n_layers x
  * layer, 1 <= layer <= 64); hop may couple sites inside a layer arbitrarily,
@@ -315,10 +315,15 @@ hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double *mu, cons
  * numbered row by row, with the row as the layer).  Anything else is EINVAL. */
 typedef struct hfqmc_lattice hfqmc_lattice; /* opaque: hopping blocks on the device */
 
-/* Validates and uploads hop (host, n_sites x n_sites row-major); allocates
- * the lattice's device copy (freed by destroy). */
-hfqmc_status hfqmc_lattice_create(hfqmc_ctx *ctx, int32_t n_sites, int32_t layer, const double *hop,
-                                  hfqmc_lattice **out);
+/* Device memory a lattice needs: its hopping blocks and a site-list buffer
+ * of n_sites entries. */
+hfqmc_status hfqmc_lattice_bytes(int32_t n_sites, int32_t layer, size_t *bytes);
+/* Validates hop (host, n_sites x n_sites row-major) and uploads its blocks
+ * into d_mem (caller-owned device memory of hfqmc_lattice_bytes, kept until
+ * destroy); the handle is library-owned.  Blocks until the upload is done. */
+hfqmc_status hfqmc_lattice_create(hfqmc_ctx *ctx, int32_t n_sites, int32_t layer, const double *hop, void *d_mem,
+                                  size_t mem_bytes, hfqmc_lattice **out);
+/* Waits for the context's stream, then frees the handle. */
 hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx *ctx, hfqmc_lattice *lat);
 /* Device workspace of hfqmc_lattice_green for n_freq frequencies
  * (1 <= n_freq <= 2048): 2 n_freq n_layers P^2 complex doubles, P the layer
@@ -336,8 +341,9 @@ hfqmc_status hfqmc_lattice_green(hfqmc_ctx *ctx, hfqmc_lattice *lat, int32_t n_f
  * and the solver's samples g(tau_l) = -W(tau_l), tau_l = l beta / L, l < L,
  * into d_weiss_tau ([j][s][l]): the level 1 / (i w - e), e = eps_s,i - mu,
  * transformed exactly, the rest summed over the n_freq frequencies and their
- * negatives.  2 <= L <= 160.  The site list is copied into a buffer of the
- * lattice, grown with hipMalloc when a longer list arrives. */
+ * negatives.  2 <= L <= 160.  The site list (at most n_sites entries) is
+ * copied into the lattice's buffer in stream order; the call returns once
+ * that copy is done. */
 hfqmc_status hfqmc_lattice_weiss(hfqmc_ctx *ctx, hfqmc_lattice *lat, int32_t n_freq, double beta, double mu,
                                  int32_t L, const double *d_eps, const double *d_gloc, const double *d_sigma,
                                  const int32_t *sites, int32_t n_sel, double *d_weiss_iw, double *d_weiss_tau);

@@ -1849,28 +1849,29 @@ hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double* mu, cons
 
 struct hfqmc_lattice {
   int n_sites = 0, layer = 0, n_layers = 0;
-  int device = 0;
-  double* d_hop = nullptr;     // n_layers blocks layer x layer, then (n_layers - 1) x layer couplings
-  int32_t* d_sites = nullptr;  // site list of the last Weiss / self-energy call
-  int sites_cap = 0;
+  double* d_hop = nullptr;     // caller's memory: n_layers blocks layer x layer, then (n_layers - 1) x layer couplings
+  int32_t* d_sites = nullptr;  // caller's memory, after the blocks: n_sites entries for a site list
 };
 
 namespace {
 
-// Copy a host site list into the lattice's device buffer (grown on demand),
-// after checking every index.
+size_t lattice_hop_doubles(int N, int b) {
+  const int nl = N / b;
+  return (size_t)nl * b * b + (size_t)(nl > 1 ? nl - 1 : 0) * b;
+}
+
+size_t lattice_mem_bytes(int N, int b) { return align_up(sizeof(double) * lattice_hop_doubles(N, b), 256) + align_up(sizeof(int32_t) * N, 256); }
+
+// Copy a host site list (indices checked, at most n_sites entries) into the
+// lattice's device buffer, in stream order after earlier calls that read it;
+// returns once the copy is done, so the host list may go at once.
 hfqmc_status lattice_sites(hfqmc_ctx* c, hfqmc_lattice* lat, const int32_t* sites, int32_t n_sel) {
+  if (n_sel > lat->n_sites) return fail(HFQMC_EINVAL, "site list of %d entries > %d sites", n_sel, lat->n_sites);
   for (int j = 0; j < n_sel; ++j)
     if (sites[j] < 0 || sites[j] >= lat->n_sites)
       return fail(HFQMC_EINVAL, "site %d of the list (%d) outside [0,%d)", j, sites[j], lat->n_sites);
-  if (n_sel > lat->sites_cap) {
-    HIP_TRY(hipStreamSynchronize(c->stream));  // earlier calls may still read the old list
-    if (lat->d_sites) HIP_TRY(hipFree(lat->d_sites));
-    lat->d_sites = nullptr;
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&lat->d_sites), sizeof(int32_t) * n_sel));
-    lat->sites_cap = n_sel;
-  }
   HIP_TRY(hipMemcpyAsync(lat->d_sites, sites, sizeof(int32_t) * n_sel, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return HFQMC_OK;
 }
 
@@ -1878,10 +1879,19 @@ hfqmc_status lattice_sites(hfqmc_ctx* c, hfqmc_lattice* lat, const int32_t* site
 
 extern "C" {
 
-hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, const double* hop,
-                                  hfqmc_lattice** out) {
-  if (!c || !hop || !out || layer < 1 || layer > kMaxLayer || n_sites < layer || n_sites % layer)
+hfqmc_status hfqmc_lattice_bytes(int32_t n_sites, int32_t layer, size_t* bytes) {
+  if (!bytes || layer < 1 || layer > kMaxLayer || n_sites < layer || n_sites % layer)
+    return fail(HFQMC_EINVAL, "hfqmc_lattice_bytes: need 1 <= layer <= %d dividing n_sites", kMaxLayer);
+  *bytes = lattice_mem_bytes(n_sites, layer);
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, const double* hop, void* d_mem,
+                                  size_t mem_bytes, hfqmc_lattice** out) {
+  if (!c || !hop || !out || !d_mem || layer < 1 || layer > kMaxLayer || n_sites < layer || n_sites % layer)
     return fail(HFQMC_EINVAL, "hfqmc_lattice_create: need 1 <= layer <= %d dividing n_sites", kMaxLayer);
+  if (mem_bytes < lattice_mem_bytes(n_sites, layer))
+    return fail(HFQMC_ENOMEM, "lattice memory %zu bytes < %zu needed", mem_bytes, lattice_mem_bytes(n_sites, layer));
   const int N = n_sites, b = layer, nl = N / b;
   double scale = 0.0;
   for (size_t k = 0; k < (size_t)N * N; ++k) {
@@ -1913,11 +1923,12 @@ hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, 
   lat->n_sites = N;
   lat->layer = b;
   lat->n_layers = nl;
-  lat->device = c->device;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&lat->d_hop), sizeof(double) * img.size());
-  if (e == hipSuccess) e = hipMemcpy(lat->d_hop, img.data(), sizeof(double) * img.size(), hipMemcpyHostToDevice);
+  lat->d_hop = reinterpret_cast<double*>(d_mem);
+  lat->d_sites = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(d_mem) +
+                                            align_up(sizeof(double) * lattice_hop_doubles(N, b), 256));
+  hipError_t e = hipMemcpyAsync(lat->d_hop, img.data(), sizeof(double) * img.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
-    if (lat->d_hop) (void)hipFree(lat->d_hop);
     delete lat;
     return fail(HFQMC_EDEVICE, "hfqmc_lattice_create: %s", hipGetErrorString(e));
   }
@@ -1929,9 +1940,7 @@ hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx* c, hfqmc_lattice* lat) {
   if (!c || !lat) return fail(HFQMC_EINVAL, "hfqmc_lattice_destroy: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   TRY(set_device(c));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  (void)hipFree(lat->d_hop);
-  if (lat->d_sites) (void)hipFree(lat->d_sites);
+  HIP_TRY(hipStreamSynchronize(c->stream));  // calls in flight may still read the caller's lattice memory
   delete lat;
   return HFQMC_OK;
 }

@@ -103,7 +103,9 @@ def lib():
                                   C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "hfqmc_entropy": [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.c_double, C.c_double, C.POINTER(C.c_double)],
-            "hfqmc_lattice_create": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(_VP)],
+            "hfqmc_lattice_bytes": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+            "hfqmc_lattice_create": [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), _VP, C.c_size_t,
+                                     C.POINTER(_VP)],
             "hfqmc_lattice_destroy": [_VP, _VP],
             "hfqmc_lattice_workspace": [_VP, C.c_int32, C.POINTER(C.c_size_t)],
             "hfqmc_lattice_green": [_VP, _VP, C.c_int32, C.c_double, C.c_double, _VP, _VP, _VP, _VP, C.c_size_t],
@@ -449,13 +451,17 @@ class Lattice:
     (2, N), sigma / gloc complex128 (2, n_freq, N)."""
 
     def __init__(self, ctx: Context, hop, layer: int):
+        torch = _torch()
         hop = np.ascontiguousarray(hop, dtype=np.float64)
         self.ctx = ctx
         self.n_sites = hop.shape[0]
         self.layer = int(layer)
+        b = C.c_size_t()
+        _check(lib().hfqmc_lattice_bytes(self.n_sites, self.layer, C.byref(b)), "hfqmc_lattice_bytes")
+        self._mem = torch.empty(b.value, dtype=torch.uint8, device=f"cuda:{ctx.device}")
         h = _VP()
-        _check(lib().hfqmc_lattice_create(ctx.h, self.n_sites, self.layer, _dp(hop), C.byref(h)),
-               "hfqmc_lattice_create")
+        _check(lib().hfqmc_lattice_create(ctx.h, self.n_sites, self.layer, _dp(hop), _VP(self._mem.data_ptr()),
+                                          b.value, C.byref(h)), "hfqmc_lattice_create")
         self.h = h
         self._ws = None
 
