@@ -76,31 +76,32 @@ class RDMFT:
                               d_dev, self.mix, self.sigma)
         return dens
 
-    def iterate(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
-                sweep_offset=0, timing=False):
-        """One full iteration; returns the solver results (solved sites), the
-        densities of all listed sites and (timing=True) the wall time of each
-        step in ms.  A site whose Weiss function is empty or full to rounding
-        (g(0+) within 1e-12 of 0 or 1, far below or above the band) is not
-        solved: its density is the Weiss function's and its self-energy stays."""
-        torch = _torch()
+    def prepare(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
+                sweep_offset=0):
+        """First half of an iteration: lattice Green function, Weiss functions
+        and the solver problems of the live sites.  A site whose Weiss
+        function is empty or full to rounding (g(0+) within 1e-12 of 0 or 1,
+        far below or above the band) is not solved: its density is the Weiss
+        function's and its self-energy stays."""
         sites = np.asarray(sites, dtype=np.int32)
-        sync = (lambda: torch.cuda.synchronize(self.dev)) if timing else (lambda: None)
-        t = [time.perf_counter()]
         w_iw, w_tau = self.weiss(sites)
-        sync()
-        t.append(time.perf_counter())
         g0 = w_tau[:, :, 0]
         live = np.all((g0 > 1e-12) & (g0 < 1.0 - 1e-12), axis=1)
-        dens = 1.0 - g0.copy()
+        idx = np.nonzero(live)[0]
+        probs = self.problems(sites[idx], w_tau[idx], n_warmup, n_measure, seed, n_bins, recompute_every, n_chains,
+                              sweep_offset)
+        return dict(sites=sites, w_iw=w_iw, w_tau=w_tau, live=live, idx=idx, problems=probs)
+
+    def finish(self, st, res):
+        """Second half: the new self-energy from the solver's results `res` (in
+        the order of st['problems']); returns the iteration's output."""
+        torch = _torch()
+        sites, live, idx, w_tau = st["sites"], st["live"], st["idx"], st["w_tau"]
+        dens = 1.0 - w_tau[:, :, 0].copy()
         dens_err = np.zeros_like(dens)
         total_err = np.zeros(len(sites))  # error of n_up + n_dn from the bins (the spins are correlated)
-        res = []
-        if live.any():
-            idx = np.nonzero(live)[0]
-            res = self.ctx.solve(self.problems(sites[idx], w_tau[idx], n_warmup, n_measure, seed, n_bins,
-                                               recompute_every, n_chains, sweep_offset))
-            t.append(time.perf_counter())
+        if len(idx):
+            w_iw = st["w_iw"]
             sub = w_iw if live.all() else w_iw[:, :, torch.as_tensor(idx, device=self.dev)].contiguous()
             dens[idx] = self.update(sites[idx], sub, res)
             dens_err[idx] = np.array([[x["n_up_err"], x["n_dn_err"]] for x in res])
@@ -108,12 +109,25 @@ class RDMFT:
             for j, x in zip(idx, res):
                 tot = x["bins"][:, 2 * L + 2] + x["bins"][:, 2 * L + 3]
                 total_err[j] = tot.std(ddof=1) / np.sqrt(tot.size)
-        else:
-            t.append(time.perf_counter())
+        return dict(results=res, density=dens, density_err=dens_err, total_err=total_err, weiss_tau=w_tau,
+                    solved=live)
+
+    def iterate(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
+                sweep_offset=0, timing=False):
+        """One full iteration (prepare, one batched solve, finish); returns the
+        solver results (live sites), the densities of all listed sites and
+        (timing=True) the wall time of each step in ms."""
+        torch = _torch()
+        sync = (lambda: torch.cuda.synchronize(self.dev)) if timing else (lambda: None)
+        t = [time.perf_counter()]
+        st = self.prepare(sites, n_warmup, n_measure, seed, n_bins, recompute_every, n_chains, sweep_offset)
         sync()
         t.append(time.perf_counter())
-        out = dict(results=res, density=dens, density_err=dens_err, total_err=total_err, weiss_tau=w_tau,
-                   solved=live)
+        res = self.ctx.solve(st["problems"]) if st["problems"] else []
+        t.append(time.perf_counter())
+        out = self.finish(st, res)
+        sync()
+        t.append(time.perf_counter())
         if timing:
             out["ms"] = dict(lattice_and_weiss=1e3 * (t[1] - t[0]), solve=1e3 * (t[2] - t[1]),
                              sigma=1e3 * (t[3] - t[2]))
@@ -137,3 +151,42 @@ class RDMFT:
             prev = d
         out["history"] = hist
         return out
+
+
+def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_iter=20, eps_after=None, **kw):
+    """converge() for several independent loops (e.g. two temperatures) that
+    share one batched solve per iteration: the solver sees all their live
+    sites at once, which fills the GPU better than one loop alone.  Each loop
+    stops once its own density change is below tol (or at max_iter).
+    seeds: one per loop.  Returns the outputs of every loop's last iteration."""
+    ctx = loops[0].ctx
+    prev = [None] * len(loops)
+    hist = [[] for _ in loops]
+    outs = [None] * len(loops)
+    active = list(range(len(loops)))
+    for it in range(max_iter):
+        states = [loops[k].prepare(sites, n_warmup, n_measure, seeds[k] + it, **kw) for k in active]
+        batch = [p for st in states for p in st["problems"]]
+        res = ctx.solve(batch) if batch else []
+        pos = 0
+        still = []
+        for k, st in zip(active, states):
+            m = len(st["problems"])
+            outs[k] = loops[k].finish(st, res[pos:pos + m])
+            pos += m
+            if it == 0 and eps_after is not None:
+                loops[k].set_eps(eps_after)
+            d = outs[k]["density"]
+            done = False
+            if prev[k] is not None:
+                hist[k].append(float(np.max(np.abs(d - prev[k]))))
+                done = hist[k][-1] < tol
+            prev[k] = d
+            if not done:
+                still.append(k)
+        active = still
+        if not active:
+            break
+    for k in range(len(loops)):
+        outs[k]["history"] = hist[k]
+    return outs

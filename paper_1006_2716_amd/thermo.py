@@ -10,7 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import hfqmc
-from .rdmft import RDMFT
+from .rdmft import RDMFT, converge_together
 
 
 def staggered_magnetization(density, coords):
@@ -20,34 +20,37 @@ def staggered_magnetization(density, coords):
     return np.where(c.sum(axis=1) % 2 == 0, 1.0, -1.0) * (d[:, 0] - d[:, 1])
 
 
-def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, L, dtau, sites, n_warmup, n_measure, seed,
+def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, sites, n_warmup, n_measure, seeds,
                  n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True):
-    """Converged densities (len(mus), len(sites), 2) at beta = L dtau for every
-    chemical potential (Hartree-shifted, ascending).  The scan starts from the
-    empty system, whose self-energy is zero, i.e. -U/2 relative to the
-    Hartree-shifted levels, and carries the self-energy from one mu to the
-    next; eps_seed (with a seed field) is used for the first iteration at
-    every mu, eps afterwards.  Also returns the errors of n_up + n_dn
-    (len(mus), len(sites)), the iteration counts and the solver proposals."""
-    beta = L * dtau
-    out = np.zeros((len(mus), len(sites), 2))
-    err = np.zeros((len(mus), len(sites)))  # of n_up + n_dn
-    iters, props = [], 0
+    """Converged densities at beta = L dtau for every L in Ls (several
+    temperatures at a fixed dtau, their loops sharing one solver batch per
+    iteration) and every chemical potential (Hartree-shifted, ascending).
+    The scan starts from the empty system, whose self-energy is zero, i.e.
+    -U/2 relative to the Hartree-shifted levels, and carries the self-energy
+    from one mu to the next; eps_seed (with a seed field) is used for the
+    first iteration at every mu, eps afterwards.  Returns per L: densities
+    (len(mus), len(sites), 2), errors of n_up + n_dn (len(mus), len(sites)),
+    iteration counts; and the solver proposals."""
     N = lattice.n_sites
     empty = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
-    sigma = empty
+    sig = [empty] * len(Ls)
+    dens = [np.zeros((len(mus), len(sites), 2)) for _ in Ls]
+    errs = [np.zeros((len(mus), len(sites))) for _ in Ls]
+    iters = [[] for _ in Ls]
+    props = 0
     for k, mu in enumerate(mus):
-        r = RDMFT(ctx, hop, layer, eps_seed, mu, U, beta, L, n_freq=n_freq,
-                  sigma0=sigma if warm_start else empty, lattice=lattice)
-        res = r.converge(sites, n_warmup, n_measure, seed + 1000 * k, tol=tol, max_iter=max_iter, eps_after=eps,
-                         n_bins=n_bins)
-        out[k] = res["density"]
-        err[k] = res["total_err"]
-        iters.append(len(res["history"]) + 1)
-        props += int(sum(x["proposals"] for x in res["results"]))
-        sigma = r.sigma.cpu().numpy()
-        r.close()
-    return out, err, iters, props
+        loops = [RDMFT(ctx, hop, layer, eps_seed, mu, U, L * dtau, L, n_freq=n_freq,
+                       sigma0=sig[a] if warm_start else empty, lattice=lattice) for a, L in enumerate(Ls)]
+        outs = converge_together(loops, sites, n_warmup, n_measure, [sd + 1000 * k for sd in seeds], tol=tol,
+                                 max_iter=max_iter, eps_after=eps, n_bins=n_bins)
+        for a, (r, o) in enumerate(zip(loops, outs)):
+            dens[a][k] = o["density"]
+            errs[a][k] = o["total_err"]
+            iters[a].append(len(o["history"]) + 1)
+            sig[a] = r.sigma.cpu().numpy()
+            r.close()
+        props += sum(int(sum(x["proposals"] for x in o["results"])) for o in outs)
+    return dens, errs, iters, props
 
 
 def entropy_error(mus, err_lo, err_hi, T_lo, T_hi):
@@ -78,14 +81,13 @@ def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites
     proposals)."""
     lat = hfqmc.Lattice(ctx, hop, layer)
     try:
-        n_lo, e_lo, it_lo, p_lo = density_scan(ctx, lat, hop, layer, eps, eps_seed, U, mus, L_hi, dtau, sites,
-                                               n_warmup, n_measure, seed, **kw)
-        n_hi, e_hi, it_hi, p_hi = density_scan(ctx, lat, hop, layer, eps, eps_seed, U, mus, L_lo, dtau, sites,
-                                               n_warmup, n_measure, seed + 7, **kw)
+        (n_lo, n_hi), (e_lo, e_hi), (it_lo, it_hi), props = density_scan(
+            ctx, lat, hop, layer, eps, eps_seed, U, mus, (L_hi, L_lo), dtau, sites, n_warmup, n_measure,
+            (seed, seed + 7), **kw)
     finally:
         lat.close()
     T_lo, T_hi = 1.0 / (L_hi * dtau), 1.0 / (L_lo * dtau)
     s = hfqmc.entropy(mus, n_lo.sum(axis=2), n_hi.sum(axis=2), T_lo, T_hi)
     s_err = entropy_error(mus, e_lo, e_hi, T_lo, T_hi)
     return dict(s=s, s_err=s_err, n_lo=n_lo, n_hi=n_hi, T_lo=T_lo, T_hi=T_hi, T=0.5 * (T_lo + T_hi),
-                iterations=it_lo + it_hi, proposals=p_lo + p_hi)
+                iterations=it_lo + it_hi, proposals=props)
