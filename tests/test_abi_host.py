@@ -117,3 +117,14 @@ def test_entropy_integral_matches_the_oracle():
         hfqmc.entropy(mu[::-1], a, b, 0.2, 0.22)
     with pytest.raises(hfqmc.HFQMCError):
         hfqmc.entropy(mu, a, b, 0.22, 0.2)
+
+
+def test_lattice_bytes_host_rules():
+    lib = hfqmc.lib()
+    b = C.c_size_t()
+    assert lib.hfqmc_lattice_bytes(441, 21, C.byref(b)) == hfqmc.OK
+    # 21 blocks of 21 x 21 doubles, 20 couplings of 21, then 441 int32 site slots (256-byte aligned parts)
+    hop = 8 * (21 * 21 * 21 + 20 * 21)
+    assert b.value == (hop + 255) // 256 * 256 + (4 * 441 + 255) // 256 * 256
+    for n, layer in ((441, 65), (440, 21), (0, 1), (20, 0)):
+        assert lib.hfqmc_lattice_bytes(n, layer, C.byref(b)) == hfqmc.EINVAL
