@@ -478,6 +478,12 @@ def main():
                    "proposals_per_step": proposals, "accept_rate": round(p_acc, 4), "delay": k,
                    "tile_rows_per_wave": rt, "graph": bool(args.graph)},
         "roofline": roofline,
+        # what bounds the launch: the impurity with the most accepted flips is
+        # one serial Markov chain; the kernel time over its accepts is the
+        # latency of one accept on the critical path
+        "critical_path": {"max_accepts": int(max(r["accepts"] for r in res)),
+                          "mean_accepts": float(np.mean([r["accepts"] for r in res])),
+                          "ns_per_accept": round(kavg * 1e6 / max(r["accepts"] for r in res), 1)},
         "max_drift": max(r["max_drift"] for r in res),
     }
     if not args.no_single:
