@@ -96,6 +96,10 @@ struct Plan {
 // kernels on full batches (L = 64: 512 impurities; L = 96, 128: about 100),
 // 1 wherever only that variant exists.
 int default_rt(int LT, int dk) {
+  // measured on MI355X: two tile rows per wave at 64/96/128; at 48 one wave
+  // per spin (three tile rows) is 25-34 % faster than three waves per spin on
+  // 325-site trapped batches at L = 40 and 48; at 32 two waves per spin win
+  if (dk == 0 && LT == 48) return 3;
   if (dk == 0 && (LT == 64 || LT == 96 || LT == 128)) return 2;
   if (dk != 0 && LT == 64) return 2;
   return 1;
