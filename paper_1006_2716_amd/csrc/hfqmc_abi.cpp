@@ -92,15 +92,16 @@ struct Plan {
   int rt = 1, dk = 0, k = 1;
 };
 
-// Untuned default tile-rows per wave: the measured best of the rank-one
-// kernels on full batches (L = 64: 512 impurities; L = 96, 128: about 100),
-// 1 wherever only that variant exists.
+// Untuned default tile-rows per wave, each the measured best of the rank-one
+// kernels on MI355X: 2 at 64 (512 impurities: 76 ms against 103 with 1 and
+// 89 with 4) and 128 (323 ms against 1404); one wave per spin at 48 (25-34 %
+// faster than three waves per spin on 325-site trapped batches, 3 % slower
+// on 100 impurities) and 96 (195 ms against 214 with 1 and 243 with 2, 105
+// impurities; 357 against 392 and 449 on 1281); 1 at 32 (two waves per spin
+// beat one by 8-10 %) and wherever only that variant exists.
 int default_rt(int LT, int dk) {
-  // measured on MI355X: two tile rows per wave at 64/96/128; at 48 one wave
-  // per spin (three tile rows) is 25-34 % faster than three waves per spin on
-  // 325-site trapped batches at L = 40 and 48; at 32 two waves per spin win
-  if (dk == 0 && LT == 48) return 3;
-  if (dk == 0 && (LT == 64 || LT == 96 || LT == 128)) return 2;
+  if (dk == 0 && (LT == 48 || LT == 96)) return 3;
+  if (dk == 0 && (LT == 64 || LT == 128)) return 2;
   if (dk != 0 && LT == 64) return 2;
   return 1;
 }

@@ -742,7 +742,8 @@ static KernelInfo info() {
 
 static const KernelInfo kKernels[] = {
     info<16, 1>(), info<32, 1>(), info<32, 2>(), info<48, 1>(), info<48, 3>(), info<64, 1>(), info<64, 2>(),
-    info<64, 4>(), info<80, 1>(), info<96, 1>(), info<96, 2>(), info<112, 1>(), info<128, 1>(), info<128, 2>(),
+    info<64, 4>(), info<80, 1>(), info<96, 1>(), info<96, 2>(), info<96, 3>(), info<112, 1>(), info<128, 1>(),
+    info<128, 2>(),
     // delayed rank-k updates, fp64 and mixed-precision flushes
     info<32, 1, 1>(), info<48, 1, 1>(), info<64, 2, 1>(), info<80, 1, 1>(), info<96, 1, 1>(), info<128, 1, 1>(),
     info<32, 1, 2>(), info<48, 1, 2>(), info<64, 2, 2>(), info<80, 1, 2>(), info<96, 1, 2>(), info<128, 1, 2>(),
