@@ -55,8 +55,8 @@ RECOMPUTE_EVERY = 50
 # HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
 # FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
 # valid only for the kernel source with this sha256 prefix.
-PROFILED_KERNEL_SHA = "1c496bc5fa2fbc3e"
-PROFILED_TRAFFIC_BYTES = 1.838e9
+PROFILED_KERNEL_SHA = "94ccf9d89011127e"
+PROFILED_TRAFFIC_BYTES = 1.747e9
 
 
 def kernel_sha() -> str:
@@ -403,7 +403,10 @@ def main():
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
     if args.workload != "headline":
-        names = ["uneven", "serving", "trapped", "slab", "rdmft", "trotter", "thermo"] \
+        # serving first: its class streams share the process's few hardware
+        # queues with whatever streams earlier legs created (measured: p50
+        # 122 ms first in the process, 235 ms after the uneven leg)
+        names = ["serving", "uneven", "trapped", "slab", "rdmft", "trotter", "thermo"] \
             if args.workload == "all" else [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
