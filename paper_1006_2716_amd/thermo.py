@@ -91,3 +91,48 @@ def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites
     s_err = entropy_error(mus, e_lo, e_hi, T_lo, T_hi)
     return dict(s=s, s_err=s_err, n_lo=n_lo, n_hi=n_hi, T_lo=T_lo, T_hi=T_hi, T=0.5 * (T_lo + T_hi),
                 iterations=it_lo + it_hi, proposals=props)
+
+
+def find_mu(ctx, hop, layer, eps, U, L, dtau, sites, target, mu_lo, mu_hi, n_warmup, n_measure, seed, tol_n=0.5,
+            max_steps=30, n_freq=500, tol=2e-3, max_iter=10, n_bins=16):
+    """Chemical potential (Hartree-shifted) for which the converged lattice
+    holds `target` atoms (n_up + n_dn summed over `sites`), by bisection on
+    [mu_lo, mu_hi] (N grows with mu); each step is a converged RDMFT loop
+    started from the nearest converged self-energy so far.  Returns
+    dict(mu, atoms, steps: [(mu, atoms)])."""
+    lat = hfqmc.Lattice(ctx, hop, layer)
+    N = lat.n_sites
+    beta = L * dtau
+    seen = []  # (mu, atoms, sigma)
+
+    def atoms_at(mu):
+        if seen:
+            sigma0 = min(seen, key=lambda t: abs(t[0] - mu))[2]
+        else:
+            sigma0 = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
+        r = RDMFT(ctx, hop, layer, eps, mu, U, beta, L, n_freq=n_freq, sigma0=sigma0, lattice=lat)
+        out = r.converge(sites, n_warmup, n_measure, seed + len(seen), tol=tol, max_iter=max_iter, n_bins=n_bins)
+        n = float(out["density"].sum())
+        seen.append((mu, n, r.sigma.cpu().numpy()))
+        r.close()
+        return n
+
+    try:
+        lo, hi = mu_lo, mu_hi
+        n_lo, n_hi = atoms_at(lo), atoms_at(hi)
+        if not (n_lo <= target <= n_hi):
+            raise ValueError(f"target {target} outside [{n_lo:.3f}, {n_hi:.3f}] on [{lo}, {hi}]")
+        mu, n = (lo, n_lo) if abs(n_lo - target) < abs(n_hi - target) else (hi, n_hi)
+        for _ in range(max_steps):
+            if abs(n - target) < tol_n:
+                break
+            mid = 0.5 * (lo + hi)
+            n_mid = atoms_at(mid)
+            if n_mid < target:
+                lo = mid
+            else:
+                hi = mid
+            mu, n = mid, n_mid
+    finally:
+        lat.close()
+    return dict(mu=mu, atoms=n, steps=[(m, a) for m, a, _ in seen])

@@ -96,3 +96,24 @@ def test_loops_sharing_a_batch_equal_separate_loops(ctx):
     finally:
         for r in together + alone:
             r.close()
+
+
+def test_find_mu_reaches_the_free_fermion_filling(ctx):
+    """U = 0: the bisection lands on the chemical potential whose exact
+    free-fermion atom number is the target."""
+    from scipy.optimize import brentq
+    from paper_1006_2716_amd.thermo import find_mu
+    hop, eps, _ = _lattice(6, 0.2)
+    sites = np.arange(36, dtype=np.int32)
+    E = np.linalg.eigvalsh(hop + np.diag(eps[0]))
+    beta, target = 4.0, 20.0
+
+    def atoms(mu):
+        return 2 * np.sum(0.5 * (1 - np.tanh(0.5 * beta * (E - mu))))
+
+    exact = brentq(lambda m: atoms(m) - target, -10, 10)
+    r = find_mu(ctx, hop, 6, eps, 0.0, 16, beta / 16, sites, target, -6.0, 6.0, 1, 4, seed=1, tol_n=1e-3,
+                max_iter=2, n_bins=2)
+    print(f"mu {r['mu']:.6f} (exact {exact:.6f}), atoms {r['atoms']:.5f}, {len(r['steps'])} loops")
+    assert abs(r["atoms"] - target) < 1e-3
+    assert abs(r["mu"] - exact) < 2e-3
