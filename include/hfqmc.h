@@ -323,7 +323,8 @@ hfqmc_status hfqmc_lattice_bytes(int32_t n_sites, int32_t layer, size_t *bytes);
  * destroy); the handle is library-owned.  Blocks until the upload is done. */
 hfqmc_status hfqmc_lattice_create(hfqmc_ctx *ctx, int32_t n_sites, int32_t layer, const double *hop, void *d_mem,
                                   size_t mem_bytes, hfqmc_lattice **out);
-/* Waits for the context's stream, then frees the handle. */
+/* Waits for the context's stream, then frees the handle.  A lattice is used
+ * only with the context that created it (EINVAL otherwise). */
 hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx *ctx, hfqmc_lattice *lat);
 /* Device workspace of hfqmc_lattice_green for n_freq frequencies
  * (1 <= n_freq <= 2048): 2 n_freq n_layers P^2 complex doubles, P the layer

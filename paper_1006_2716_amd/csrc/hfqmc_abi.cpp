@@ -1853,6 +1853,7 @@ hfqmc_status hfqmc_entropy(int32_t n_mu, int32_t n_sites, const double* mu, cons
 }  // extern "C"
 
 struct hfqmc_lattice {
+  hfqmc_ctx* ctx = nullptr;    // the context that created it (its calls take no other)
   int n_sites = 0, layer = 0, n_layers = 0;
   double* d_hop = nullptr;     // caller's memory: n_layers blocks layer x layer, then (n_layers - 1) x layer couplings
   int32_t* d_sites = nullptr;  // caller's memory, after the blocks: n_sites entries for a site list
@@ -1925,6 +1926,7 @@ hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, 
   TRY(set_device(c));
   hfqmc_lattice* lat = new (std::nothrow) hfqmc_lattice;
   if (!lat) return fail(HFQMC_ENOMEM, "out of host memory");
+  lat->ctx = c;
   lat->n_sites = N;
   lat->layer = b;
   lat->n_layers = nl;
@@ -1942,7 +1944,7 @@ hfqmc_status hfqmc_lattice_create(hfqmc_ctx* c, int32_t n_sites, int32_t layer, 
 }
 
 hfqmc_status hfqmc_lattice_destroy(hfqmc_ctx* c, hfqmc_lattice* lat) {
-  if (!c || !lat) return fail(HFQMC_EINVAL, "hfqmc_lattice_destroy: bad arguments");
+  if (!c || !lat || lat->ctx != c) return fail(HFQMC_EINVAL, "hfqmc_lattice_destroy: bad arguments");
   std::lock_guard<std::mutex> g(c->mu);
   TRY(set_device(c));
   HIP_TRY(hipStreamSynchronize(c->stream));  // calls in flight may still read the caller's lattice memory
@@ -1963,6 +1965,7 @@ hfqmc_status hfqmc_lattice_green(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_fre
   if (!c || !lat || !d_eps || !d_sigma || !d_gloc || !d_ws || n_freq < 1 || n_freq > kMaxFreq || !(beta > 0) ||
       !std::isfinite(beta) || !std::isfinite(mu))
     return fail(HFQMC_EINVAL, "hfqmc_lattice_green: bad arguments");
+  if (lat->ctx != c) return fail(HFQMC_EINVAL, "hfqmc_lattice_green: lattice of another context");
   const size_t need = lattice_work_bytes(lat->layer, lat->n_layers, n_freq);
   if (ws_bytes < need) return fail(HFQMC_ENOMEM, "lattice workspace %zu bytes < %zu needed", ws_bytes, need);
   std::lock_guard<std::mutex> g(c->mu);
@@ -1991,6 +1994,7 @@ hfqmc_status hfqmc_lattice_weiss(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_fre
       n_freq < 1 || n_freq > kMaxFreq || L < 2 || L > kMaxL || !(beta > 0) || !std::isfinite(beta) ||
       !std::isfinite(mu))
     return fail(HFQMC_EINVAL, "hfqmc_lattice_weiss: bad arguments");
+  if (lat->ctx != c) return fail(HFQMC_EINVAL, "hfqmc_lattice_weiss: lattice of another context");
   std::lock_guard<std::mutex> g(c->mu);
   TRY(set_device(c));
   TRY(lattice_sites(c, lat, sites, n_sel));
@@ -2019,6 +2023,7 @@ hfqmc_status hfqmc_lattice_sigma(hfqmc_ctx* c, hfqmc_lattice* lat, int32_t n_fre
       n_freq < 1 || n_freq > kMaxFreq || L < 2 || L > kMaxL || !(beta > 0) || !std::isfinite(beta) ||
       !std::isfinite(mu) || !(U >= 0) || !std::isfinite(U) || !(mix > 0 && mix <= 1))
     return fail(HFQMC_EINVAL, "hfqmc_lattice_sigma: bad arguments");
+  if (lat->ctx != c) return fail(HFQMC_EINVAL, "hfqmc_lattice_sigma: lattice of another context");
   std::vector<int32_t> sorted(sites, sites + n_sel);
   std::sort(sorted.begin(), sorted.end());
   if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())

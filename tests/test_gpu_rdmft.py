@@ -233,8 +233,16 @@ def test_invalid_lattices_and_lists_raise(ctx):
     with pytest.raises(hfqmc.HFQMCError):
         hfqmc.Lattice(ctx, big, 65)
     lat = hfqmc.Lattice(ctx, hop, 5)
+    other = hfqmc.Context(0)
     try:
         s0 = torch.zeros((2, 4, 20), dtype=torch.complex128, device="cuda:0")
+        ws = torch.empty(lat.workspace_size(4), dtype=torch.uint8, device="cuda:0")
+        gl = torch.empty((2, 4, 20), dtype=torch.complex128, device="cuda:0")
+        e_t = _t(eps)
+        st = hfqmc.lib().hfqmc_lattice_green(other.h, lat.h, 4, 3.0, mu, hfqmc._VP(e_t.data_ptr()),
+                                             hfqmc._VP(s0.data_ptr()), hfqmc._VP(gl.data_ptr()),
+                                             hfqmc._VP(ws.data_ptr()), ws.numel())
+        assert st == hfqmc.EINVAL  # a lattice works only with the context that created it
         gl = lat.green(4, 3.0, mu, _t(eps), s0)
         with pytest.raises(hfqmc.HFQMCError):
             lat.weiss(4, 3.0, mu, 8, _t(eps), gl, s0, [0, 20])
@@ -244,3 +252,4 @@ def test_invalid_lattices_and_lists_raise(ctx):
                              device="cuda:0"), torch.zeros((2, 2), dtype=torch.float64, device="cuda:0"), 1.0, s0)
     finally:
         lat.close()
+        other.close()
