@@ -23,6 +23,7 @@ Other workloads (one JSON line each, --workload NAME or all):
            U = 8, dtau = 0.25, 5000 sweeps, 200 sites x 10 DMFT iterations
            with device-resident state: p50/p99 latency and throughput;
            --serve-chains N splits each L = 160 request into N chains
+           (serving_chains: the same stream with 4 chains per L = 160 request)
   trapped  21x21 trap (V0 = 0.05, U = 8, beta = 10, L = 40, AF seed), the
            325 sites with n > 1e-3, 1000 + 10000 sweeps, fp64
   slab     41x41 trap (V0 = 0.02, U = 8, beta = 16, L = 80, ~1000 atoms,
@@ -205,7 +206,10 @@ def bench_serving(args):
     st = ctx.serve_stats()
     ctx.close()
     out.pop("results")
-    _line("HF-QMC serving: p99 request latency (Poisson 200 req/s)", out["p99_ms"], "ms", 1, 0, wall * 1e3,
+    name = "HF-QMC serving: p99 request latency (Poisson 200 req/s)"
+    if args.serve_chains > 1:
+        name += f", L = 160 requests as {args.serve_chains} chains"
+    _line(name, out["p99_ms"], "ms", 1, 0, wall * 1e3,
           {"workload": "Poisson 200 req/s, L in {20,40,80,160} weights 4:3:2:1, U=8, dtau=0.25, 5000 sweeps "
                        "(500 warm-up first, 100 later), 200 sites x 10 DMFT iterations, state on device",
            "step_ms": args.step_ms, "quantum_proposals": args.quantum, "chains_L160": max(1, args.serve_chains),
@@ -371,8 +375,8 @@ def bench_thermo(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "trapped", "slab", "rdmft", "trotter", "thermo",
-                             "all"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "serving_chains", "trapped", "slab", "rdmft",
+                             "trotter", "thermo", "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -406,7 +410,7 @@ def main():
         # serving first: its class streams share the process's few hardware
         # queues with whatever streams earlier legs created (measured: p50
         # 122 ms first in the process, 235 ms after the uneven leg)
-        names = ["serving", "uneven", "trapped", "slab", "rdmft", "trotter", "thermo"] \
+        names = ["serving", "serving_chains", "uneven", "trapped", "slab", "rdmft", "trotter", "thermo"] \
             if args.workload == "all" else [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
@@ -414,6 +418,8 @@ def main():
                 bench_uneven(args)
             elif n == "serving":
                 bench_serving(args)
+            elif n == "serving_chains":
+                bench_serving(argparse.Namespace(**dict(vars(args), serve_chains=4)))
             elif n == "rdmft":
                 bench_rdmft(args)
             elif n == "trotter":
