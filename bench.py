@@ -406,12 +406,22 @@ def main():
         print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a design "
                                    "note only (impurities shard with no exchange), not built"}))
         sys.exit(2)
+    if args.workload == "all":
+        # every leg in a process of its own: kernel-class concurrency depends
+        # on how the process's streams map onto its few hardware queues, which
+        # shifts with the streams earlier contexts created (measured: serving
+        # p50 122 ms first in a process, 235 ms after the uneven leg); this
+        # process never touches the GPU itself
+        import subprocess
+        rc = 0
+        for n in ["uneven", "serving", "serving_chains", "trapped", "slab", "rdmft", "trotter", "thermo"]:
+            print(f"== {n}", file=sys.stderr, flush=True)
+            cmd = [sys.executable, os.path.abspath(__file__), "--workload", n, "--steps", str(args.steps), "--warmup",
+                   str(args.warmup), "--step-ms", str(args.step_ms), "--quantum", str(args.quantum)]
+            rc = subprocess.run(cmd).returncode or rc
+        sys.exit(rc)
     if args.workload != "headline":
-        # serving first: its class streams share the process's few hardware
-        # queues with whatever streams earlier legs created (measured: p50
-        # 122 ms first in the process, 235 ms after the uneven leg)
-        names = ["serving", "serving_chains", "uneven", "trapped", "slab", "rdmft", "trotter", "thermo"] \
-            if args.workload == "all" else [args.workload]
+        names = [args.workload]
         for n in names:
             print(f"== {n}", file=sys.stderr, flush=True)
             if n == "uneven":
