@@ -41,6 +41,7 @@ class RDMFT:
         else:
             self.sigma = torch.as_tensor(np.asarray(sigma0, dtype=np.complex128), device=self.dev).contiguous()
         self.gloc = None
+        self.fields = {}  # site -> final fields of its last solve (used with keep_fields)
 
     def close(self):
         if self.own_lattice:
@@ -77,12 +78,14 @@ class RDMFT:
         return dens
 
     def prepare(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
-                sweep_offset=0):
+                sweep_offset=0, keep_fields=False):
         """First half of an iteration: lattice Green function, Weiss functions
         and the solver problems of the live sites.  A site whose Weiss
         function is empty or full to rounding (g(0+) within 1e-12 of 0 or 1,
         far below or above the band) is not solved: its density is the Weiss
-        function's and its self-energy stays."""
+        function's and its self-energy stays.  keep_fields: a site solved
+        before starts from its last final fields (all its chains) instead of
+        drawn ones, so a short warm-up suffices."""
         sites = np.asarray(sites, dtype=np.int32)
         w_iw, w_tau = self.weiss(sites)
         g0 = w_tau[:, :, 0]
@@ -90,6 +93,11 @@ class RDMFT:
         idx = np.nonzero(live)[0]
         probs = self.problems(sites[idx], w_tau[idx], n_warmup, n_measure, seed, n_bins, recompute_every, n_chains,
                               sweep_offset)
+        if keep_fields:
+            for p in probs:
+                f = self.fields.get(p["site"])
+                if f is not None:
+                    p["init_fields"] = f
         return dict(sites=sites, w_iw=w_iw, w_tau=w_tau, live=live, idx=idx, problems=probs)
 
     def finish(self, st, res):
@@ -105,6 +113,8 @@ class RDMFT:
             sub = w_iw if live.all() else w_iw[:, :, torch.as_tensor(idx, device=self.dev)].contiguous()
             dens[idx] = self.update(sites[idx], sub, res)
             dens_err[idx] = np.array([[x["n_up_err"], x["n_dn_err"]] for x in res])
+            for j, x in zip(idx, res):
+                self.fields[int(sites[j])] = x["fields"].copy()
             L = self.L
             for j, x in zip(idx, res):
                 tot = x["bins"][:, 2 * L + 2] + x["bins"][:, 2 * L + 3]
@@ -113,14 +123,15 @@ class RDMFT:
                     solved=live)
 
     def iterate(self, sites, n_warmup, n_measure, seed, n_bins=32, recompute_every=50, n_chains=0,
-                sweep_offset=0, timing=False):
+                sweep_offset=0, timing=False, keep_fields=False):
         """One full iteration (prepare, one batched solve, finish); returns the
         solver results (live sites), the densities of all listed sites and
         (timing=True) the wall time of each step in ms."""
         torch = _torch()
         sync = (lambda: torch.cuda.synchronize(self.dev)) if timing else (lambda: None)
         t = [time.perf_counter()]
-        st = self.prepare(sites, n_warmup, n_measure, seed, n_bins, recompute_every, n_chains, sweep_offset)
+        st = self.prepare(sites, n_warmup, n_measure, seed, n_bins, recompute_every, n_chains, sweep_offset,
+                          keep_fields)
         sync()
         t.append(time.perf_counter())
         res = self.ctx.solve(st["problems"]) if st["problems"] else []
@@ -133,14 +144,20 @@ class RDMFT:
                              sigma=1e3 * (t[3] - t[2]))
         return out
 
-    def converge(self, sites, n_warmup, n_measure, seed, tol=2e-3, max_iter=20, eps_after=None, **kw):
+    def converge(self, sites, n_warmup, n_measure, seed, tol=2e-3, max_iter=20, eps_after=None,
+                 n_warmup_next=None, **kw):
         """Iterate until the largest density change between iterations is below
         tol (or max_iter).  eps_after (e.g. without the seed field) replaces
-        the site energies after the first iteration.  Returns the last
-        iteration's output with 'history' (density change per iteration)."""
+        the site energies after the first iteration.  n_warmup_next: later
+        iterations start every site from its previous final fields with this
+        many warm-up sweeps.  Returns the last iteration's output with
+        'history' (density change per iteration)."""
         prev, hist = None, []
         for it in range(max_iter):
-            out = self.iterate(sites, n_warmup, n_measure, seed + it, **kw)
+            if it > 0 and n_warmup_next is not None:
+                out = self.iterate(sites, n_warmup_next, n_measure, seed + it, keep_fields=True, **kw)
+            else:
+                out = self.iterate(sites, n_warmup, n_measure, seed + it, **kw)
             if it == 0 and eps_after is not None:
                 self.set_eps(eps_after)
             d = out["density"]
@@ -153,19 +170,23 @@ class RDMFT:
         return out
 
 
-def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_iter=20, eps_after=None, **kw):
+def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_iter=20, eps_after=None,
+                      n_warmup_next=None, **kw):
     """converge() for several independent loops (e.g. two temperatures) that
     share one batched solve per iteration: the solver sees all their live
     sites at once, which fills the GPU better than one loop alone.  Each loop
     stops once its own density change is below tol (or at max_iter).
-    seeds: one per loop.  Returns the outputs of every loop's last iteration."""
+    seeds: one per loop; n_warmup_next as in converge().  Returns the outputs
+    of every loop's last iteration."""
     ctx = loops[0].ctx
     prev = [None] * len(loops)
     hist = [[] for _ in loops]
     outs = [None] * len(loops)
     active = list(range(len(loops)))
     for it in range(max_iter):
-        states = [loops[k].prepare(sites, n_warmup, n_measure, seeds[k] + it, **kw) for k in active]
+        warm = it > 0 and n_warmup_next is not None
+        states = [loops[k].prepare(sites, n_warmup_next if warm else n_warmup, n_measure, seeds[k] + it,
+                                   keep_fields=warm, **kw) for k in active]
         batch = [p for st in states for p in st["problems"]]
         res = ctx.solve(batch) if batch else []
         pos = 0

@@ -253,3 +253,28 @@ def test_invalid_lattices_and_lists_raise(ctx):
     finally:
         lat.close()
         other.close()
+
+
+def test_iterations_from_previous_fields_match_oracle(ctx):
+    """keep_fields: the second iteration starts every site from its first
+    iteration's final fields (short warm-up); the oracle run from the same
+    fields gives the same chains."""
+    from paper_1006_2716_amd.rdmft import RDMFT
+    hop, eps, mu, _ = _lattice(3, 4, V0=0.1, mu_eff=0.2, h=0.1)
+    U, beta, L, nf = 5.0, 4.0, 16, 100
+    sites = np.arange(12, dtype=np.int32)
+    r = RDMFT(ctx, hop, 4, eps, mu, U, beta, L, n_freq=nf)
+    try:
+        first = r.iterate(sites, 30, 200, seed=4, n_bins=8)
+        sig1 = r.sigma.cpu().numpy()
+        second = r.iterate(sites, 3, 200, seed=5, n_bins=8, keep_fields=True)
+        _, wt, _ = _oracle_iteration(hop, eps, mu, U, beta, L, nf, sig1, sites, 3, 200, 5, 8)
+        assert np.max(np.abs(second["weiss_tau"] - wt)) < 1e-12
+        probs = [dict(L=L, beta=beta, U=U, weiss=wt[j], n_warmup=3, n_measure=200, recompute_every=50, n_bins=8,
+                      seed=5, site=int(sites[j]), init_fields=first["results"][j]["fields"]) for j in range(12)]
+        ref = oracle.run(probs, n_threads=8)
+        for g, o in zip(second["results"], ref):
+            assert np.array_equal(g["fields"], o["fields"])
+            assert np.max(np.abs(g["bins"] - o["bins"])) < 1e-9
+    finally:
+        r.close()
