@@ -84,26 +84,39 @@ struct EngineG : SliceState<C::JW> {
   // of the current G from G0 in memory plus the pending panel terms.
   __device__ __forceinline__ void append(int l, double fu, double fd) {
     auto& P = sm.u.p;
-    for (int it = tid; it < 4 * LT; it += C::NTH) {
+    // work items (spin, column|row, index) tid, tid + NTH, ...: every G0 load
+    // of a thread is issued before the first is used (above 128 slices a
+    // quarter of the threads take two items; one memory round trip, not two)
+    constexpr int NI = (4 * LT + C::NTH - 1) / C::NTH;
+    double g0[NI];
+    static_for<NI>([&](auto k) __attribute__((always_inline)) {
+      const int it = tid + k * C::NTH;
       const int s = it / (2 * LT), v = (it / LT) & 1, i = it % LT;
       const double* Gs = gm + (size_t)s * LT * LT;
-      if (i >= L) {  // padding rows/columns stay exactly zero
-        (v == 0 ? P.pa : P.pb)[s][kb][i] = 0.0;
-      } else if (v == 0) {
-        double x = Gs[(size_t)i * LT + l];
+      g0[k] = (it < 4 * LT && i < L) ? (v == 0 ? Gs[(size_t)i * LT + l] : Gs[(size_t)l * LT + i]) : 0.0;
+    });
+    static_for<NI>([&](auto k) __attribute__((always_inline)) {
+      const int it = tid + k * C::NTH;
+      if (it < 4 * LT) {
+        const int s = it / (2 * LT), v = (it / LT) & 1, i = it % LT;
+        if (i >= L) {  // padding rows/columns stay exactly zero
+          (v == 0 ? P.pa : P.pb)[s][kb][i] = 0.0;
+        } else if (v == 0) {
+          double x = g0[k];
 #pragma unroll
-        for (int j = 0; j < KP; ++j)  // unrolled: all panel reads issue at once
-          if (j < kb) x = __builtin_fma(P.pa[s][j][i], P.pb[s][j][l], x);
-        if (i == l) x -= 1.0;
-        P.pa[s][kb][i] = (s ? fd : fu) * x;
-      } else {
-        double x = Gs[(size_t)l * LT + i];
+          for (int j = 0; j < KP; ++j)  // unrolled: all panel reads issue at once
+            if (j < kb) x = __builtin_fma(P.pa[s][j][i], P.pb[s][j][l], x);
+          if (i == l) x -= 1.0;
+          P.pa[s][kb][i] = (s ? fd : fu) * x;
+        } else {
+          double x = g0[k];
 #pragma unroll
-        for (int j = 0; j < KP; ++j)
-          if (j < kb) x = __builtin_fma(P.pa[s][j][l], P.pb[s][j][i], x);
-        P.pb[s][kb][i] = x;
+          for (int j = 0; j < KP; ++j)
+            if (j < kb) x = __builtin_fma(P.pa[s][j][l], P.pb[s][j][i], x);
+          P.pb[s][kb][i] = x;
+        }
       }
-    }
+    });
     __syncthreads();
     static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
