@@ -60,17 +60,29 @@ PROFILED_KERNEL_SHA = "94ccf9d89011127e"
 PROFILED_TRAFFIC_BYTES = 1.747e9
 
 
-def kernel_sha() -> str:
-    """sha256 prefix of the register-tile sweep kernel's sources."""
+# lattice Green function kernel (21 x 21 trap, 500 frequencies x 2 spins):
+# FETCH_SIZE x 1.9997 + WRITE_SIZE of one launch, almost all of it the
+# workspace round trip of the left-connected inverses
+PROFILED_LATTICE_SHA = "8bb37110995ab5b7"
+PROFILED_LATTICE_TRAFFIC_BYTES = 6.866e8
+
+
+def kernel_sha(files=("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h")) -> str:
+    """sha256 prefix of a kernel's sources (default: the register-tile sweep kernel)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1006_2716_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def kernel_traffic():
     return PROFILED_TRAFFIC_BYTES if kernel_sha() == PROFILED_KERNEL_SHA else None
+
+
+def lattice_traffic():
+    same = kernel_sha(("hfqmc_lattice.hip", "hfqmc_lattice.h")) == PROFILED_LATTICE_SHA
+    return PROFILED_LATTICE_TRAFFIC_BYTES if same else None
 
 
 def algorithmic_flops(L: int, p_acc: float, n_rec: int = RECOMPUTE_EVERY, kbar: float = 0.0) -> float:
@@ -305,7 +317,9 @@ def bench_rdmft(args):
                        "325 sites with n>1e-3, their 1000+10000-sweep solve, self-energy update"},
           lattice_roofline={"bound": "alu", "kernel": "hfqmc::rgf_kernel<32>",
                             "achieved": round(c2["lattice_tflops"], 3), "peak": 78.6, "unit": "TFLOP/s",
-                            "frac": round(c2["lattice_tflops"] / 78.6, 4), "traffic": None},
+                            "frac": round(c2["lattice_tflops"] / 78.6, 4), "traffic": lattice_traffic(),
+                            "hbm_gbps": (round(lattice_traffic() / (c2["lattice_green_ms"] * 1e-3) / 1e9, 1)
+                                         if lattice_traffic() else None)},
           parts=parts)
 
 
