@@ -270,8 +270,8 @@ def _lattice_flops(layer, n_layers):
 
 def bench_rdmft(args):
     """One RDMFT iteration of the 21 x 21 trap (lattice Green function at 500
-    frequencies, Weiss functions, the 325-site solve, self-energy), and the
-    lattice part alone on the 41 x 41 trap."""
+    frequencies, Weiss functions, the 325-site solve, self-energy), and one
+    of the 41 x 41 trap (1281 sites at L = 80)."""
     import torch
     from paper_1006_2716_amd import hfqmc, workloads
     from paper_1006_2716_amd.rdmft import RDMFT
@@ -300,11 +300,11 @@ def bench_rdmft(args):
         leg = dict(sites=n * n, solved_sites=int(len(sites)), n_freq=nf, lattice_green_ms=green_ms,
                    weiss_ms=weiss_ms, lattice_tflops=flops / (green_ms * 1e-3) / 1e12,
                    lattice_flops=flops)
-        if name == "21x21":
-            it = r.iterate(sites, n_warmup=1000, n_measure=10000, seed=2, timing=True)
-            props = int(sum(x["proposals"] for x in it["results"]))
-            leg.update(iteration_ms=sum(it["ms"].values()), steps_ms=it["ms"], proposals=props,
-                       atoms=float(it["density"].sum()))
+        # one full iteration of each trap (the 41 x 41 one solves 1281 sites at L = 80)
+        it = r.iterate(sites, n_warmup=1000, n_measure=10000, seed=2 if name == "21x21" else 5, timing=True)
+        props = int(sum(x["proposals"] for x in it["results"]))
+        leg.update(iteration_ms=sum(it["ms"].values()), steps_ms=it["ms"], proposals=props,
+                   atoms=float(it["density"].sum()))
         parts[name] = leg
         r.close()
         ctx.close()
