@@ -300,7 +300,11 @@ def bench_rdmft(args):
         leg = dict(sites=n * n, solved_sites=int(len(sites)), n_freq=nf, lattice_green_ms=green_ms,
                    weiss_ms=weiss_ms, lattice_tflops=flops / (green_ms * 1e-3) / 1e12,
                    lattice_flops=flops)
-        # one full iteration of each trap (the 41 x 41 one solves 1281 sites at L = 80)
+        # one full iteration of each trap (the 41 x 41 one solves 1281 sites at L = 80), after an untimed
+        # short one on a throwaway loop (the first solve of a process loads the sweep kernels)
+        rw = RDMFT(ctx, hop, n, eps, mu_eff, U, beta, L, n_freq=nf, lattice=r.lat)
+        rw.iterate(sites, n_warmup=2, n_measure=4, seed=1, n_bins=2)
+        rw.close()
         it = r.iterate(sites, n_warmup=1000, n_measure=10000, seed=2 if name == "21x21" else 5, timing=True)
         props = int(sum(x["proposals"] for x in it["results"]))
         leg.update(iteration_ms=sum(it["ms"].values()), steps_ms=it["ms"], proposals=props,
