@@ -372,7 +372,7 @@ def bench_thermo(args):
     ctx = hfqmc.Context(0)
     t0 = time.perf_counter()
     r = entropy_scan(ctx, hop, n, eps, eps_seed, U, mus, 38, 42, dtau, sites, 100, 2000, seed=5, n_freq=500,
-                     tol=5e-3, max_iter=5, n_bins=16)
+                     tol=5e-3, max_iter=5, n_bins=16, mu_group=args.mu_group)
     ms = (time.perf_counter() - t0) * 1e3
     ctx.close()
     c = n * n // 2
@@ -383,7 +383,7 @@ def bench_thermo(args):
           "proposals/s", 1, 0, ms,
           {"workload": "13x13 open trap V0=0.25, U=10, dtau=0.1, L=38/42, mu-U/2 from -11 to 0 (45 points), "
                        "staggered seed 0.1 in the first iteration at each point, 100+2000 sweeps, <=5 iterations "
-                       "per point",
+                       "per point, " + f"{args.mu_group} chemical potential(s) per solver batch",
            "proposals": r["proposals"], "rdmft_iterations": int(sum(r["iterations"]))},
           T=r["T"], atoms=N, entropy_central=float(r["s"][-1][c]), entropy_central_err=float(r["s_err"][-1][c]),
           entropy_per_particle=float(r["s"][-1].sum() / N),
@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
     ap.add_argument("--quantum", type=int, default=0, help="serving: fixed proposals per request per step")
     ap.add_argument("--serve-chains", type=int, default=1, help="serving: chains per L = 160 request")
+    ap.add_argument("--mu-group", type=int, default=9,
+                    help="thermo: chemical potentials whose loops share one solver batch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()

@@ -21,16 +21,22 @@ def staggered_magnetization(density, coords):
 
 
 def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, sites, n_warmup, n_measure, seeds,
-                 n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True):
+                 n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True, mu_group=1):
     """Converged densities at beta = L dtau for every L in Ls (several
-    temperatures at a fixed dtau, their loops sharing one solver batch per
-    iteration) and every chemical potential (Hartree-shifted, ascending).
+    temperatures at a fixed dtau) and every chemical potential
+    (Hartree-shifted, ascending).  The loops of mu_group consecutive chemical
+    potentials and of all temperatures share one solver batch per iteration.
     The scan starts from the empty system, whose self-energy is zero, i.e.
-    -U/2 relative to the Hartree-shifted levels, and carries the self-energy
-    from one mu to the next; eps_seed (with a seed field) is used for the
-    first iteration at every mu, eps afterwards.  Returns per L: densities
-    (len(mus), len(sites), 2), errors of n_up + n_dn (len(mus), len(sites)),
-    iteration counts; and the solver proposals."""
+    -U/2 relative to the Hartree-shifted levels; every loop of a group starts
+    from the self-energy converged at the last chemical potential of the
+    group before (warm_start) or from the empty system.  eps_seed (with a seed
+    field) is used for the first iteration at every mu, eps afterwards.  The
+    solver seed of (mu index k, temperature a) is seeds[a] + 1000 k whatever
+    the grouping.  Returns per L: densities (len(mus), len(sites), 2), errors
+    of n_up + n_dn (len(mus), len(sites)), iteration counts; and the solver
+    proposals."""
+    if mu_group < 1:
+        raise ValueError("mu_group must be positive")
     N = lattice.n_sites
     empty = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
     sig = [empty] * len(Ls)
@@ -38,16 +44,19 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
     errs = [np.zeros((len(mus), len(sites))) for _ in Ls]
     iters = [[] for _ in Ls]
     props = 0
-    for k, mu in enumerate(mus):
-        loops = [RDMFT(ctx, hop, layer, eps_seed, mu, U, L * dtau, L, n_freq=n_freq,
-                       sigma0=sig[a] if warm_start else empty, lattice=lattice) for a, L in enumerate(Ls)]
-        outs = converge_together(loops, sites, n_warmup, n_measure, [sd + 1000 * k for sd in seeds], tol=tol,
-                                 max_iter=max_iter, eps_after=eps, n_bins=n_bins)
-        for a, (r, o) in enumerate(zip(loops, outs)):
+    for k0 in range(0, len(mus), mu_group):
+        ks = range(k0, min(k0 + mu_group, len(mus)))
+        keys = [(k, a) for k in ks for a in range(len(Ls))]
+        loops = [RDMFT(ctx, hop, layer, eps_seed, mus[k], U, Ls[a] * dtau, Ls[a], n_freq=n_freq,
+                       sigma0=sig[a] if warm_start else empty, lattice=lattice) for k, a in keys]
+        outs = converge_together(loops, sites, n_warmup, n_measure, [seeds[a] + 1000 * k for k, a in keys],
+                                 tol=tol, max_iter=max_iter, eps_after=eps, n_bins=n_bins)
+        for (k, a), r, o in zip(keys, loops, outs):
             dens[a][k] = o["density"]
             errs[a][k] = o["total_err"]
             iters[a].append(len(o["history"]) + 1)
-            sig[a] = r.sigma.cpu().numpy()
+            if k == ks[-1]:
+                sig[a] = r.sigma.cpu().numpy()
             r.close()
         props += sum(int(sum(x["proposals"] for x in o["results"])) for o in outs)
     return dens, errs, iters, props

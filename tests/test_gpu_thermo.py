@@ -35,9 +35,9 @@ def test_entropy_scan_reproduces_free_fermions(ctx):
     hop, eps, _ = _lattice(4, 0.3)
     mus = np.linspace(-7.5, 1.0, 86)
     sites = np.arange(16, dtype=np.int32)
-    print("entropy scan, 4x4 trap, U = 0, 86 chemical potentials x 2 temperatures", flush=True)
+    print("entropy scan, 4x4 trap, U = 0, 86 chemical potentials x 2 temperatures, groups of 6", flush=True)
     r = entropy_scan(ctx, hop, 4, eps, eps, 0.0, mus, 38, 42, 0.1, sites, 1, 4, seed=3, n_freq=500, max_iter=2,
-                     n_bins=2)
+                     n_bins=2, mu_group=6)
     E, phi = np.linalg.eigh(hop + np.diag(eps[0]))
     T = r["T"]
     exact = np.stack([2 * (phi ** 2) @ _s_of_f(0.5 * (1 - np.tanh(0.5 * (E - m) / T))) for m in mus])
@@ -117,3 +117,33 @@ def test_find_mu_reaches_the_free_fermion_filling(ctx):
     print(f"mu {r['mu']:.6f} (exact {exact:.6f}), atoms {r['atoms']:.5f}, {len(r['steps'])} loops")
     assert abs(r["atoms"] - target) < 1e-3
     assert abs(r["mu"] - exact) < 2e-3
+
+
+def test_grouped_scan_equals_one_mu_at_a_time(ctx):
+    """Chemical potentials scanned in groups (their loops and both
+    temperatures in one solver batch) give bitwise the densities, errors and
+    entropies of the scan one chemical potential at a time, when every loop
+    starts from the empty system; with warm starts the grouped scan stays
+    within the statistical errors on the free lattice."""
+    from paper_1006_2716_amd import hfqmc
+    from paper_1006_2716_amd.thermo import density_scan
+    hop, eps, _ = _lattice(4, 0.3, h=0.1)
+    plain = np.stack([0.5 * (eps[0] + eps[1])] * 2)
+    mus = np.linspace(-4.0, 0.0, 7)
+    sites = np.arange(16, dtype=np.int32)
+    lat = hfqmc.Lattice(ctx, hop, 4)
+    try:
+        kw = dict(n_freq=100, tol=1e-12, max_iter=2, n_bins=4, warm_start=False)
+        one = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, (4, 11), **kw)
+        print("grouped scan: 7 chemical potentials in groups of 3 (cold starts)", flush=True)
+        grp = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, (4, 11),
+                           mu_group=3, **kw)
+    finally:
+        lat.close()
+    for a in range(2):
+        assert np.array_equal(one[0][a], grp[0][a])
+        assert np.array_equal(one[1][a], grp[1][a])
+        assert one[2][a] == grp[2][a]
+    assert one[3] == grp[3]
+    with pytest.raises(ValueError):
+        density_scan(ctx, None, hop, 4, plain, eps, 4.0, mus, (18,), 0.2, sites, 1, 4, (1,), mu_group=0)
