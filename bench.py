@@ -270,8 +270,9 @@ def _lattice_flops(layer, n_layers):
 
 def bench_rdmft(args):
     """One RDMFT iteration of the 21 x 21 trap (lattice Green function at 500
-    frequencies, Weiss functions, the 325-site solve, self-energy), and one
-    of the 41 x 41 trap (1281 sites at L = 80)."""
+    frequencies, Weiss functions, the 325-site solve, self-energy), the same
+    with 2 chains per site, and one iteration of the 41 x 41 trap (1281 sites
+    at L = 80)."""
     import torch
     from paper_1006_2716_amd import hfqmc, workloads
     from paper_1006_2716_amd.rdmft import RDMFT
@@ -309,6 +310,15 @@ def bench_rdmft(args):
         props = int(sum(x["proposals"] for x in it["results"]))
         leg.update(iteration_ms=sum(it["ms"].values()), steps_ms=it["ms"], proposals=props,
                    atoms=float(it["density"].sum()))
+        if name == "21x21":
+            # the same iteration with every site split into 2 chains (each with the full warm-up and half
+            # the measured sweeps): 650 units fill the GPU better than 325
+            r2 = RDMFT(ctx, hop, n, eps, mu_eff, U, beta, L, n_freq=nf, lattice=r.lat)
+            it2 = r2.iterate(sites, n_warmup=1000, n_measure=10000, seed=2, timing=True, n_chains=2)
+            r2.close()
+            leg["two_chains"] = dict(iteration_ms=sum(it2["ms"].values()), steps_ms=it2["ms"],
+                                     proposals=int(sum(x["proposals"] for x in it2["results"])),
+                                     atoms=float(it2["density"].sum()))
         parts[name] = leg
         r.close()
         ctx.close()
