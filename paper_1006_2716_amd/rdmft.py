@@ -151,13 +151,15 @@ class RDMFT:
         the site energies after the first iteration.  n_warmup_next: later
         iterations start every site from its previous final fields with this
         many warm-up sweeps.  Returns the last iteration's output with
-        'history' (density change per iteration)."""
-        prev, hist = None, []
+        'history' (density change per iteration) and 'proposals_all' (solver
+        proposals of every iteration)."""
+        prev, hist, total = None, [], 0
         for it in range(max_iter):
             if it > 0 and n_warmup_next is not None:
                 out = self.iterate(sites, n_warmup_next, n_measure, seed + it, keep_fields=True, **kw)
             else:
                 out = self.iterate(sites, n_warmup, n_measure, seed + it, **kw)
+            total += _proposals(out["results"])
             if it == 0 and eps_after is not None:
                 self.set_eps(eps_after)
             d = out["density"]
@@ -167,7 +169,12 @@ class RDMFT:
                     break
             prev = d
         out["history"] = hist
+        out["proposals_all"] = total
         return out
+
+
+def _proposals(results):
+    return int(sum(int(x["proposals"]) for x in results))
 
 
 def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_iter=20, eps_after=None,
@@ -177,10 +184,12 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
     sites at once, which fills the GPU better than one loop alone.  Each loop
     stops once its own density change is below tol (or at max_iter).
     seeds: one per loop; n_warmup_next as in converge().  Returns the outputs
-    of every loop's last iteration."""
+    of every loop's last iteration, with 'history' and 'proposals_all' as in
+    converge()."""
     ctx = loops[0].ctx
     prev = [None] * len(loops)
     hist = [[] for _ in loops]
+    total = [0] * len(loops)
     outs = [None] * len(loops)
     active = list(range(len(loops)))
     for it in range(max_iter):
@@ -194,6 +203,7 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
         for k, st in zip(active, states):
             m = len(st["problems"])
             outs[k] = loops[k].finish(st, res[pos:pos + m])
+            total[k] += _proposals(res[pos:pos + m])
             pos += m
             if it == 0 and eps_after is not None:
                 loops[k].set_eps(eps_after)
@@ -210,4 +220,5 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
             break
     for k in range(len(loops)):
         outs[k]["history"] = hist[k]
+        outs[k]["proposals_all"] = total[k]
     return outs

@@ -34,7 +34,7 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
     solver seed of (mu index k, temperature a) is seeds[a] + 1000 k whatever
     the grouping.  Returns per L: densities (len(mus), len(sites), 2), errors
     of n_up + n_dn (len(mus), len(sites)), iteration counts; and the solver
-    proposals."""
+    proposals of all iterations."""
     if mu_group < 1:
         raise ValueError("mu_group must be positive")
     N = lattice.n_sites
@@ -58,7 +58,7 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
             if k == ks[-1]:
                 sig[a] = r.sigma.cpu().numpy()
             r.close()
-        props += sum(int(sum(x["proposals"] for x in o["results"])) for o in outs)
+        props += sum(o["proposals_all"] for o in outs)
     return dens, errs, iters, props
 
 

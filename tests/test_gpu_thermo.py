@@ -75,7 +75,8 @@ def test_half_filling_is_particle_hole_symmetric(ctx):
 def test_loops_sharing_a_batch_equal_separate_loops(ctx):
     """Two temperatures iterated together (one solver batch per iteration)
     give bitwise the densities and self-energies of separate loops: batch
-    composition never changes a result."""
+    composition never changes a result.  The loops' proposal counts cover
+    every iteration's solve."""
     from paper_1006_2716_amd.rdmft import RDMFT, converge_together
     hop, eps, _ = _lattice(5, 0.2, h=0.1)
     plain = np.stack([0.5 * (eps[0] + eps[1])] * 2)
@@ -86,13 +87,27 @@ def test_loops_sharing_a_batch_equal_separate_loops(ctx):
         return [RDMFT(ctx, hop, 5, eps, 0.3, 4.0, L * 0.25, L, n_freq=100) for L in (14, 18)]
 
     together = make()
-    outs = converge_together(together, sites, 20, 200, [3, 9], tol=1e-9, max_iter=3, eps_after=plain, **kw)
+    seen = []  # proposals of every solver call, counted independently of the loops' bookkeeping
+    solve = ctx.solve
+
+    def counting(problems):
+        res = solve(problems)
+        seen.append(sum(int(x["proposals"]) for x in res))
+        return res
+
+    ctx.solve = counting
+    try:
+        outs = converge_together(together, sites, 20, 200, [3, 9], tol=1e-9, max_iter=3, eps_after=plain, **kw)
+    finally:
+        del ctx.solve
+    assert len(seen) == 3 and sum(o["proposals_all"] for o in outs) == sum(seen)
     alone = make()
     try:
         for k, r in enumerate(alone):
             o = r.converge(sites, 20, 200, [3, 9][k], tol=1e-9, max_iter=3, eps_after=plain, **kw)
             assert np.array_equal(o["density"], outs[k]["density"])
             assert np.array_equal(r.sigma.cpu().numpy(), together[k].sigma.cpu().numpy())
+            assert o["proposals_all"] == outs[k]["proposals_all"]
     finally:
         for r in together + alone:
             r.close()
