@@ -403,7 +403,14 @@ def bench_thermo(args):
           T=r["T"], atoms=N, entropy_central=float(r["s"][-1][c]), entropy_central_err=float(r["s_err"][-1][c]),
           entropy_per_particle=float(r["s"][-1].sum() / N),
           entropy_per_particle_err=float(np.sqrt((r["s_err"][-1] ** 2).sum()) / N),
-          m_stag_central=float(m[c]), m_stag_max=float(np.abs(m).max()))
+          m_stag_central=float(m[c]), m_stag_max=float(np.abs(m).max()),
+          # largest change of a spin density (the loops' 5e-3 tolerance) and of n_up + n_dn in each (mu, T)
+          # point's last iteration
+          points=int(r["last_change"].shape[0]), points_below_tol=int(np.sum(r["last_change"][:, 0] < 5e-3)),
+          last_change_median=float(np.nanmedian(r["last_change"][:, 0])),
+          last_change_max=float(np.nanmax(r["last_change"][:, 0])),
+          last_change_total_median=float(np.nanmedian(r["last_change"][:, 1])),
+          last_change_total_max=float(np.nanmax(r["last_change"][:, 1])))
 
 
 def main():

@@ -151,9 +151,10 @@ class RDMFT:
         the site energies after the first iteration.  n_warmup_next: later
         iterations start every site from its previous final fields with this
         many warm-up sweeps.  Returns the last iteration's output with
-        'history' (density change per iteration) and 'proposals_all' (solver
-        proposals of every iteration)."""
-        prev, hist, total = None, [], 0
+        'history' (largest change of a spin density per iteration),
+        'history_total' (the same for n_up + n_dn) and 'proposals_all'
+        (solver proposals of every iteration)."""
+        prev, hist, hist_tot, total = None, [], [], 0
         for it in range(max_iter):
             if it > 0 and n_warmup_next is not None:
                 out = self.iterate(sites, n_warmup_next, n_measure, seed + it, keep_fields=True, **kw)
@@ -165,10 +166,12 @@ class RDMFT:
             d = out["density"]
             if prev is not None:
                 hist.append(float(np.max(np.abs(d - prev))))
+                hist_tot.append(float(np.max(np.abs(d.sum(axis=1) - prev.sum(axis=1)))))
                 if hist[-1] < tol:
                     break
             prev = d
         out["history"] = hist
+        out["history_total"] = hist_tot
         out["proposals_all"] = total
         return out
 
@@ -184,11 +187,12 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
     sites at once, which fills the GPU better than one loop alone.  Each loop
     stops once its own density change is below tol (or at max_iter).
     seeds: one per loop; n_warmup_next as in converge().  Returns the outputs
-    of every loop's last iteration, with 'history' and 'proposals_all' as in
-    converge()."""
+    of every loop's last iteration, with 'history', 'history_total' and
+    'proposals_all' as in converge()."""
     ctx = loops[0].ctx
     prev = [None] * len(loops)
     hist = [[] for _ in loops]
+    hist_tot = [[] for _ in loops]
     total = [0] * len(loops)
     outs = [None] * len(loops)
     active = list(range(len(loops)))
@@ -211,6 +215,7 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
             done = False
             if prev[k] is not None:
                 hist[k].append(float(np.max(np.abs(d - prev[k]))))
+                hist_tot[k].append(float(np.max(np.abs(d.sum(axis=1) - prev[k].sum(axis=1)))))
                 done = hist[k][-1] < tol
             prev[k] = d
             if not done:
@@ -220,5 +225,6 @@ def converge_together(loops, sites, n_warmup, n_measure, seeds, tol=2e-3, max_it
             break
     for k in range(len(loops)):
         outs[k]["history"] = hist[k]
+        outs[k]["history_total"] = hist_tot[k]
         outs[k]["proposals_all"] = total[k]
     return outs

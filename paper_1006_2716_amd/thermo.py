@@ -33,7 +33,9 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
     field) is used for the first iteration at every mu, eps afterwards.  The
     solver seed of (mu index k, temperature a) is seeds[a] + 1000 k whatever
     the grouping.  Returns per L: densities (len(mus), len(sites), 2), errors
-    of n_up + n_dn (len(mus), len(sites)), iteration counts; and the solver
+    of n_up + n_dn (len(mus), len(sites)), iteration counts, the largest
+    change of a spin density and of n_up + n_dn in each point's last
+    iteration (len(mus), 2) (NaN after a single iteration); and the solver
     proposals of all iterations."""
     if mu_group < 1:
         raise ValueError("mu_group must be positive")
@@ -43,6 +45,7 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
     dens = [np.zeros((len(mus), len(sites), 2)) for _ in Ls]
     errs = [np.zeros((len(mus), len(sites))) for _ in Ls]
     iters = [[] for _ in Ls]
+    last = [np.full((len(mus), 2), np.nan) for _ in Ls]
     props = 0
     for k0 in range(0, len(mus), mu_group):
         ks = range(k0, min(k0 + mu_group, len(mus)))
@@ -55,11 +58,13 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
             dens[a][k] = o["density"]
             errs[a][k] = o["total_err"]
             iters[a].append(len(o["history"]) + 1)
+            if o["history"]:
+                last[a][k] = o["history"][-1], o["history_total"][-1]
             if k == ks[-1]:
                 sig[a] = r.sigma.cpu().numpy()
             r.close()
         props += sum(o["proposals_all"] for o in outs)
-    return dens, errs, iters, props
+    return dens, errs, iters, props, last
 
 
 def entropy_error(mus, err_lo, err_hi, T_lo, T_hi):
@@ -87,10 +92,10 @@ def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites
     T_lo = 1/(L_hi dtau) on the grid mus (the first point taken as empty).
     Returns dict(s (len(mus), sites), s_err (statistical, from the last
     iteration's bins at every point), n_lo, n_hi, T_lo, T_hi, T, iterations,
-    proposals)."""
+    last_change (density_scan's, both temperatures), proposals)."""
     lat = hfqmc.Lattice(ctx, hop, layer)
     try:
-        (n_lo, n_hi), (e_lo, e_hi), (it_lo, it_hi), props = density_scan(
+        (n_lo, n_hi), (e_lo, e_hi), (it_lo, it_hi), props, (c_lo, c_hi) = density_scan(
             ctx, lat, hop, layer, eps, eps_seed, U, mus, (L_hi, L_lo), dtau, sites, n_warmup, n_measure,
             (seed, seed + 7), **kw)
     finally:
@@ -99,7 +104,7 @@ def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites
     s = hfqmc.entropy(mus, n_lo.sum(axis=2), n_hi.sum(axis=2), T_lo, T_hi)
     s_err = entropy_error(mus, e_lo, e_hi, T_lo, T_hi)
     return dict(s=s, s_err=s_err, n_lo=n_lo, n_hi=n_hi, T_lo=T_lo, T_hi=T_hi, T=0.5 * (T_lo + T_hi),
-                iterations=it_lo + it_hi, proposals=props)
+                iterations=it_lo + it_hi, last_change=np.concatenate([c_lo, c_hi]), proposals=props)
 
 
 def find_mu(ctx, hop, layer, eps, U, L, dtau, sites, target, mu_lo, mu_hi, n_warmup, n_measure, seed, tol_n=0.5,

@@ -108,6 +108,8 @@ def test_loops_sharing_a_batch_equal_separate_loops(ctx):
             assert np.array_equal(o["density"], outs[k]["density"])
             assert np.array_equal(r.sigma.cpu().numpy(), together[k].sigma.cpu().numpy())
             assert o["proposals_all"] == outs[k]["proposals_all"]
+            assert o["history_total"] == outs[k]["history_total"] and len(o["history_total"]) == 2
+            assert all(t <= 2 * h for t, h in zip(o["history_total"], o["history"]))
     finally:
         for r in together + alone:
             r.close()
@@ -159,6 +161,8 @@ def test_grouped_scan_equals_one_mu_at_a_time(ctx):
         assert np.array_equal(one[0][a], grp[0][a])
         assert np.array_equal(one[1][a], grp[1][a])
         assert one[2][a] == grp[2][a]
+        assert np.array_equal(one[4][a], grp[4][a])
+        assert np.all(np.isfinite(one[4][a])) and np.all(one[4][a] >= 0)
     assert one[3] == grp[3]
     with pytest.raises(ValueError):
         density_scan(ctx, None, hop, 4, plain, eps, 4.0, mus, (18,), 0.2, sites, 1, 4, (1,), mu_group=0)
