@@ -142,68 +142,144 @@ def lam(dtau: float, U: float) -> float:
     return out.value
 
 
+def _struct_dtype(S):
+    """numpy dtype with the field offsets of ctypes Structure S (pointers as
+    uint64 addresses), for filling or reading arrays of S column-wise."""
+    names, formats, offsets = [], [], []
+    for name, ct in S._fields_:
+        shape = ()
+        if issubclass(ct, C.Array):
+            shape, ct = (ct._length_,), ct._type_
+        if issubclass(ct, C._Pointer):
+            f = "<u8"
+        else:
+            f = {C.c_double: "<f8", C.c_int32: "<i4", C.c_int64: "<i8", C.c_uint64: "<u8"}[ct]
+        names.append(name)
+        formats.append((f, shape) if shape else f)
+        offsets.append(getattr(S, name).offset)
+    return np.dtype(dict(names=names, formats=formats, offsets=offsets, itemsize=C.sizeof(S)))
+
+
+def _view(arr, dt):
+    return np.frombuffer((C.c_char * C.sizeof(arr)).from_buffer(arr), dtype=dt)
+
+
+def _addr(a):
+    return a.__array_interface__["data"][0]
+
+
+_U64 = (1 << 64) - 1  # seeds and site ids wrap to 64 bits, as a ctypes uint64 field does
+
+
 class _Problems:
-    """Marshals problem dicts into an array of Problem structs (keeps buffers alive)."""
+    """Marshals problem dicts into an array of Problem structs; the Weiss
+    samples and initial fields of all problems are packed into one buffer
+    each, which this object keeps alive."""
+
+    _dt = None
 
     def __init__(self, problems):
-        self.keep = []
+        if _Problems._dt is None:
+            _Problems._dt = _struct_dtype(Problem)
         n = len(problems)
         self.arr = (Problem * max(n, 1))()
-        for i, p in enumerate(problems):
-            L = int(p["L"])
-            w = np.ascontiguousarray(p["weiss"], dtype=np.float64).reshape(2, L)
-            wu, wd = np.ascontiguousarray(w[0]), np.ascontiguousarray(w[1])
-            init = p.get("init_fields")
-            ia = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
-            self.keep += [wu, wd, ia]
-            pr = self.arr[i]
-            pr.L = L
-            pr.beta = float(p["beta"])
-            pr.U = float(p["U"])
-            pr.weiss[0] = _dp(wu)
-            pr.weiss[1] = _dp(wd)
-            pr.n_warmup = int(p["n_warmup"])
-            pr.n_measure = int(p["n_measure"])
-            pr.recompute_every = int(p.get("recompute_every", 50))
-            pr.n_bins = int(p["n_bins"])
-            pr.seed = int(p["seed"])
-            pr.site_id = int(p.get("site", i))
-            pr.sweep_offset = int(p.get("sweep_offset", 0))
-            pr.init_fields = None if ia is None else ia.ctypes.data_as(C.POINTER(C.c_int8))
-            pr.delay = int(p.get("delay", 0))
-            pr.n_chains = int(p.get("n_chains", 0))
         self.n = n
+        if n == 0:
+            self.keep = []
+            return
+        Ls = np.array([int(p["L"]) for p in problems], dtype=np.int64)
+        ws = []
+        for p, L in zip(problems, Ls.tolist()):
+            w = np.asarray(p["weiss"], dtype=np.float64)
+            if w.size != 2 * L:
+                raise ValueError(f"weiss of {w.size} samples for L = {L} (need 2 x L)")
+            ws.append(w.reshape(-1))
+        weiss = np.concatenate(ws)
+        w_off = np.concatenate([[0], np.cumsum(2 * Ls)[:-1]])
+        inits = [p.get("init_fields") for p in problems]
+        has = [k for k, f in enumerate(inits) if f is not None]
+        init_buf = None
+        v = _view(self.arr, self._dt)
+        if has:
+            parts = []
+            for k in has:
+                f = np.asarray(inits[k], dtype=np.int8).reshape(-1)
+                if f.size != Ls[k]:
+                    raise ValueError(f"init_fields of {f.size} entries for L = {int(Ls[k])}")
+                parts.append(f)
+            init_buf = np.concatenate(parts)
+            i_off = np.concatenate([[0], np.cumsum(Ls[has])[:-1]])
+            v["init_fields"][has] = _addr(init_buf) + i_off
+        self.keep = [weiss, init_buf]
+        base = _addr(weiss)
+        v["L"] = Ls
+        v["beta"] = [float(p["beta"]) for p in problems]
+        v["U"] = [float(p["U"]) for p in problems]
+        v["weiss"][:, 0] = base + 8 * w_off
+        v["weiss"][:, 1] = base + 8 * (w_off + Ls)
+        v["n_warmup"] = [int(p["n_warmup"]) for p in problems]
+        v["n_measure"] = [int(p["n_measure"]) for p in problems]
+        v["recompute_every"] = [int(p.get("recompute_every", 50)) for p in problems]
+        v["n_bins"] = [int(p["n_bins"]) for p in problems]
+        v["seed"] = [int(p["seed"]) & _U64 for p in problems]
+        v["site_id"] = [int(p.get("site", i)) & _U64 for i, p in enumerate(problems)]
+        v["sweep_offset"] = [int(p.get("sweep_offset", 0)) for p in problems]
+        v["delay"] = [int(p.get("delay", 0)) for p in problems]
+        v["n_chains"] = [int(p.get("n_chains", 0)) for p in problems]
 
 
 class _Results:
+    """Result structs pointing into one buffer per output (g, g_err, bins,
+    final fields) for all problems; to_list() returns per-problem views."""
+
+    _dt = None
+
     def __init__(self, problems):
+        if _Results._dt is None:
+            _Results._dt = _struct_dtype(Result)
         n = len(problems)
         self.arr = (Result * max(n, 1))()
-        self.bufs = []
-        for i, p in enumerate(problems):
-            L = int(p["L"])
-            g = np.zeros((2, L + 1))
-            ge = np.zeros((2, L + 1))
-            bins = np.zeros((int(p["n_bins"]), 2 * (L + 1) + 3))
-            ff = np.zeros(L, dtype=np.int8)
-            self.bufs.append((g, ge, bins, ff))
-            r = self.arr[i]
-            r.g[0] = g[0].ctypes.data_as(C.POINTER(C.c_double))
-            r.g[1] = g[1].ctypes.data_as(C.POINTER(C.c_double))
-            r.g_err[0] = ge[0].ctypes.data_as(C.POINTER(C.c_double))
-            r.g_err[1] = ge[1].ctypes.data_as(C.POINTER(C.c_double))
-            r.bins = _dp(bins)
-            r.final_fields = ff.ctypes.data_as(C.POINTER(C.c_int8))
+        self.n = n
+        self.Ls = np.array([int(p["L"]) for p in problems], dtype=np.int64)
+        self.nbs = np.array([int(p["n_bins"]) for p in problems], dtype=np.int64)
+        L1 = self.Ls + 1
+        self.g_off = np.concatenate([[0], np.cumsum(2 * L1)[:-1]]).astype(np.int64)
+        self.b_off = np.concatenate([[0], np.cumsum(self.nbs * (2 * L1 + 3))[:-1]]).astype(np.int64)
+        self.f_off = np.concatenate([[0], np.cumsum(self.Ls)[:-1]]).astype(np.int64)
+        self.g = np.zeros(int((2 * L1).sum()))
+        self.ge = np.zeros_like(self.g)
+        self.bins = np.zeros(int((self.nbs * (2 * L1 + 3)).sum()))
+        self.ff = np.zeros(int(self.Ls.sum()), dtype=np.int8)
+        if n == 0:
+            return
+        v = _view(self.arr, self._dt)
+        v["g"][:, 0] = _addr(self.g) + 8 * self.g_off
+        v["g"][:, 1] = _addr(self.g) + 8 * (self.g_off + L1)
+        v["g_err"][:, 0] = _addr(self.ge) + 8 * self.g_off
+        v["g_err"][:, 1] = _addr(self.ge) + 8 * (self.g_off + L1)
+        v["bins"] = _addr(self.bins) + 8 * self.b_off
+        v["final_fields"] = _addr(self.ff) + self.f_off
 
     def to_list(self):
+        if self.n == 0:
+            return []
+        v = _view(self.arr, self._dt)
+        n_ = v["n"].tolist()
+        ne = v["n_err"].tolist()
+        cols = {k: v[k].tolist() for k in ("docc", "docc_err", "accept_rate", "max_drift", "proposals", "accepts",
+                                            "nonpositive", "status")}
         out = []
-        for i, (g, ge, bins, ff) in enumerate(self.bufs):
-            r = self.arr[i]
-            out.append(dict(g_up=g[0].copy(), g_dn=g[1].copy(), g_up_err=ge[0].copy(), g_dn_err=ge[1].copy(),
-                            bins=bins.copy(), fields=ff.copy(), n_up=r.n[0], n_dn=r.n[1], n_up_err=r.n_err[0],
-                            n_dn_err=r.n_err[1], docc=r.docc, docc_err=r.docc_err, accept_rate=r.accept_rate,
-                            max_drift=r.max_drift, proposals=r.proposals, accepts=r.accepts,
-                            nonpositive=r.nonpositive, status=r.status))
+        for i, (L, nb, go, bo, fo) in enumerate(zip(self.Ls.tolist(), self.nbs.tolist(), self.g_off.tolist(),
+                                                    self.b_off.tolist(), self.f_off.tolist())):
+            w = L + 1
+            out.append(dict(g_up=self.g[go:go + w], g_dn=self.g[go + w:go + 2 * w], g_up_err=self.ge[go:go + w],
+                            g_dn_err=self.ge[go + w:go + 2 * w],
+                            bins=self.bins[bo:bo + nb * (2 * w + 3)].reshape(nb, 2 * w + 3),
+                            fields=self.ff[fo:fo + L], n_up=n_[i][0], n_dn=n_[i][1], n_up_err=ne[i][0],
+                            n_dn_err=ne[i][1], docc=cols["docc"][i], docc_err=cols["docc_err"][i],
+                            accept_rate=cols["accept_rate"][i], max_drift=cols["max_drift"][i],
+                            proposals=cols["proposals"][i], accepts=cols["accepts"][i],
+                            nonpositive=cols["nonpositive"][i], status=cols["status"][i]))
         return out
 
 

@@ -128,3 +128,71 @@ def test_lattice_bytes_host_rules():
     assert b.value == (hop + 255) // 256 * 256 + (4 * 441 + 255) // 256 * 256
     for n, layer in ((441, 65), (440, 21), (0, 1), (20, 0)):
         assert lib.hfqmc_lattice_bytes(n, layer, C.byref(b)) == hfqmc.EINVAL
+
+
+def test_problem_marshalling_places_every_field():
+    """The packed Problem structs hold each problem's scalars, and their
+    pointers reach that problem's Weiss samples and initial fields (read back
+    through ctypes, as the library reads them)."""
+    rng = np.random.default_rng(4)
+    probs = []
+    for i, L in enumerate((5, 16, 1, 33, 7)):
+        p = dict(L=L, beta=1.0 + i, U=0.5 * i, weiss=rng.random((2, L)), n_warmup=10 + i, n_measure=100 + i,
+                 n_bins=2 + i, seed=2 ** 63 + i if i == 3 else i, site=7 * i)
+        if i in (1, 3):
+            p["init_fields"] = rng.choice([-1, 1], size=L)
+        if i == 2:
+            p.update(recompute_every=3, sweep_offset=-5, delay=4, n_chains=2, seed=-1)
+        probs.append(p)
+    P = hfqmc._Problems(probs)
+    assert P.n == 5
+    for i, p in enumerate(probs):
+        s = P.arr[i]
+        L = p["L"]
+        assert (s.L, s.beta, s.U, s.n_warmup, s.n_measure, s.n_bins) == (L, p["beta"], p["U"], p["n_warmup"],
+                                                                        p["n_measure"], p["n_bins"])
+        assert s.seed == p["seed"] % 2 ** 64 and s.site_id == p["site"]
+        assert (s.recompute_every, s.sweep_offset, s.delay, s.n_chains) == (
+            p.get("recompute_every", 50), p.get("sweep_offset", 0), p.get("delay", 0), p.get("n_chains", 0))
+        for sp in range(2):
+            assert [s.weiss[sp][k] for k in range(L)] == p["weiss"][sp].tolist()
+        if "init_fields" in p:
+            assert [s.init_fields[k] for k in range(L)] == p["init_fields"].tolist()
+        else:
+            assert not s.init_fields
+    with pytest.raises(ValueError):
+        hfqmc._Problems([dict(probs[0], weiss=np.zeros((2, 4)))])
+    with pytest.raises(ValueError):
+        hfqmc._Problems([dict(probs[0], init_fields=np.ones(4))])
+    assert hfqmc._Problems([]).n == 0
+
+
+def test_result_buffers_are_disjoint_and_read_back():
+    """Each Result struct points at its own regions of the shared output
+    buffers; values written through those pointers come back in to_list()."""
+    probs = [dict(L=L, n_bins=nb) for L, nb in ((3, 2), (16, 4), (1, 3))]
+    R = hfqmc._Results(probs)
+    for i, p in enumerate(probs):
+        r = R.arr[i]
+        L, nb = p["L"], p["n_bins"]
+        for sp in range(2):
+            for k in range(L + 1):
+                r.g[sp][k] = 1000 * i + 100 * sp + k
+                r.g_err[sp][k] = -(1000 * i + 100 * sp + k)
+        for k in range(nb * (2 * (L + 1) + 3)):
+            r.bins[k] = 10000 * i + k
+        for k in range(L):
+            r.final_fields[k] = 1 if (i + k) % 2 else -1
+        r.n[0], r.n[1], r.proposals, r.status = 0.25 + i, 0.5 + i, 17 * i, -i
+    out = R.to_list()
+    for i, (p, o) in enumerate(zip(probs, out)):
+        L, nb = p["L"], p["n_bins"]
+        assert o["g_up"].tolist() == [1000 * i + k for k in range(L + 1)]
+        assert o["g_dn"].tolist() == [1000 * i + 100 + k for k in range(L + 1)]
+        assert o["g_dn_err"].tolist() == [-(1000 * i + 100 + k) for k in range(L + 1)]
+        assert o["bins"].shape == (nb, 2 * (L + 1) + 3)
+        assert o["bins"].reshape(-1).tolist() == [10000 * i + k for k in range(o["bins"].size)]
+        assert o["fields"].tolist() == [1 if (i + k) % 2 else -1 for k in range(L)]
+        assert (o["n_up"], o["n_dn"], o["proposals"], o["status"]) == (0.25 + i, 0.5 + i, 17 * i, -i)
+        assert isinstance(o["proposals"], int) and isinstance(o["n_up"], float)
+    assert hfqmc._Results([]).to_list() == []
