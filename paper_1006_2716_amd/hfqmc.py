@@ -229,57 +229,34 @@ class _Problems:
 
 
 class _Results:
-    """Result structs pointing into one buffer per output (g, g_err, bins,
-    final fields) for all problems; to_list() returns per-problem views."""
-
-    _dt = None
-
     def __init__(self, problems):
-        if _Results._dt is None:
-            _Results._dt = _struct_dtype(Result)
         n = len(problems)
         self.arr = (Result * max(n, 1))()
-        self.n = n
-        self.Ls = np.array([int(p["L"]) for p in problems], dtype=np.int64)
-        self.nbs = np.array([int(p["n_bins"]) for p in problems], dtype=np.int64)
-        L1 = self.Ls + 1
-        self.g_off = np.concatenate([[0], np.cumsum(2 * L1)[:-1]]).astype(np.int64)
-        self.b_off = np.concatenate([[0], np.cumsum(self.nbs * (2 * L1 + 3))[:-1]]).astype(np.int64)
-        self.f_off = np.concatenate([[0], np.cumsum(self.Ls)[:-1]]).astype(np.int64)
-        self.g = np.zeros(int((2 * L1).sum()))
-        self.ge = np.zeros_like(self.g)
-        self.bins = np.zeros(int((self.nbs * (2 * L1 + 3)).sum()))
-        self.ff = np.zeros(int(self.Ls.sum()), dtype=np.int8)
-        if n == 0:
-            return
-        v = _view(self.arr, self._dt)
-        v["g"][:, 0] = _addr(self.g) + 8 * self.g_off
-        v["g"][:, 1] = _addr(self.g) + 8 * (self.g_off + L1)
-        v["g_err"][:, 0] = _addr(self.ge) + 8 * self.g_off
-        v["g_err"][:, 1] = _addr(self.ge) + 8 * (self.g_off + L1)
-        v["bins"] = _addr(self.bins) + 8 * self.b_off
-        v["final_fields"] = _addr(self.ff) + self.f_off
+        self.bufs = []
+        for i, p in enumerate(problems):
+            L = int(p["L"])
+            g = np.zeros((2, L + 1))
+            ge = np.zeros((2, L + 1))
+            bins = np.zeros((int(p["n_bins"]), 2 * (L + 1) + 3))
+            ff = np.zeros(L, dtype=np.int8)
+            self.bufs.append((g, ge, bins, ff))
+            r = self.arr[i]
+            r.g[0] = g[0].ctypes.data_as(C.POINTER(C.c_double))
+            r.g[1] = g[1].ctypes.data_as(C.POINTER(C.c_double))
+            r.g_err[0] = ge[0].ctypes.data_as(C.POINTER(C.c_double))
+            r.g_err[1] = ge[1].ctypes.data_as(C.POINTER(C.c_double))
+            r.bins = _dp(bins)
+            r.final_fields = ff.ctypes.data_as(C.POINTER(C.c_int8))
 
     def to_list(self):
-        if self.n == 0:
-            return []
-        v = _view(self.arr, self._dt)
-        n_ = v["n"].tolist()
-        ne = v["n_err"].tolist()
-        cols = {k: v[k].tolist() for k in ("docc", "docc_err", "accept_rate", "max_drift", "proposals", "accepts",
-                                            "nonpositive", "status")}
         out = []
-        for i, (L, nb, go, bo, fo) in enumerate(zip(self.Ls.tolist(), self.nbs.tolist(), self.g_off.tolist(),
-                                                    self.b_off.tolist(), self.f_off.tolist())):
-            w = L + 1
-            out.append(dict(g_up=self.g[go:go + w], g_dn=self.g[go + w:go + 2 * w], g_up_err=self.ge[go:go + w],
-                            g_dn_err=self.ge[go + w:go + 2 * w],
-                            bins=self.bins[bo:bo + nb * (2 * w + 3)].reshape(nb, 2 * w + 3),
-                            fields=self.ff[fo:fo + L], n_up=n_[i][0], n_dn=n_[i][1], n_up_err=ne[i][0],
-                            n_dn_err=ne[i][1], docc=cols["docc"][i], docc_err=cols["docc_err"][i],
-                            accept_rate=cols["accept_rate"][i], max_drift=cols["max_drift"][i],
-                            proposals=cols["proposals"][i], accepts=cols["accepts"][i],
-                            nonpositive=cols["nonpositive"][i], status=cols["status"][i]))
+        for i, (g, ge, bins, ff) in enumerate(self.bufs):
+            r = self.arr[i]
+            out.append(dict(g_up=g[0].copy(), g_dn=g[1].copy(), g_up_err=ge[0].copy(), g_dn_err=ge[1].copy(),
+                            bins=bins.copy(), fields=ff.copy(), n_up=r.n[0], n_dn=r.n[1], n_up_err=r.n_err[0],
+                            n_dn_err=r.n_err[1], docc=r.docc, docc_err=r.docc_err, accept_rate=r.accept_rate,
+                            max_drift=r.max_drift, proposals=r.proposals, accepts=r.accepts,
+                            nonpositive=r.nonpositive, status=r.status))
         return out
 
 

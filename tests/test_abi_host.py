@@ -168,8 +168,8 @@ def test_problem_marshalling_places_every_field():
 
 
 def test_result_buffers_are_disjoint_and_read_back():
-    """Each Result struct points at its own regions of the shared output
-    buffers; values written through those pointers come back in to_list()."""
+    """Each Result struct points at its own output arrays; values written
+    through those pointers come back in to_list()."""
     probs = [dict(L=L, n_bins=nb) for L, nb in ((3, 2), (16, 4), (1, 3))]
     R = hfqmc._Results(probs)
     for i, p in enumerate(probs):
