@@ -92,12 +92,33 @@ def algorithmic_flops(L: int, p_acc: float, n_rec: int = RECOMPUTE_EVERY, kbar: 
     return 4.0 * p_acc * L * L + 8.0 * p_acc * L * kbar + (16.0 / 3.0) * L * L / n_rec + 2.0 * L
 
 
+def host_cpu():
+    """CPU model (from /proc/cpuinfo), logical CPUs of the host, CPUs this
+    process may run on, and the threads the oracle uses: the host-core share
+    this process is given (OMP_NUM_THREADS when set), else every CPU of its
+    affinity mask."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    threads = int(share) if share.isdigit() and int(share) > 0 else affinity
+    return dict(model=model, nproc=os.cpu_count() or 1, affinity=affinity, threads=min(threads, affinity))
+
+
 def cpu_baseline(probs, seconds_hint: float = 12.0, chunk: int = 128):
     """The oracle on the host's cores: impurities of the step in order, a
     chunk at a time (at least one), until the whole step is done or
     seconds_hint has passed (a bounded sample on a slow host)."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    cpu = host_cpu()
+    threads = cpu["threads"]
     done, props = 0, 0
     t0 = time.perf_counter()
     while done < len(probs) and (done == 0 or time.perf_counter() - t0 < seconds_hint):
@@ -107,6 +128,9 @@ def cpu_baseline(probs, seconds_hint: float = 12.0, chunk: int = 128):
     dt = time.perf_counter() - t0
     what = "all" if done == len(probs) else f"first {done} of"
     return dict(value=props / dt, unit="proposals/s", cores=threads, kind="oracle",
+                per_core=props / dt / threads, cpu_model=cpu["model"], host_nproc=cpu["nproc"],
+                affinity_cpus=cpu["affinity"],
+                threads_rule="OMP_NUM_THREADS (this process's host-core share) if set, else the affinity mask",
                 sample=f"{what} {len(probs)} impurities in chunks of {chunk}, full {probs[0]['n_warmup']}+"
                        f"{probs[0]['n_measure']} sweeps ({props} proposals, {dt:.1f} s)")
 

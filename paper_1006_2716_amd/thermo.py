@@ -12,6 +12,25 @@ import numpy as np
 from . import hfqmc
 from .rdmft import RDMFT, converge_together
 
+# A converged loop draws solver seed base + it in its iteration it (< max_iter),
+# so loop bases are spaced SEED_STRIDE apart: every (point, temperature,
+# iteration) of a scan, and every bisection step of find_mu, gets a Philox key
+# of its own (keys that coincide would replay the same fields and uniforms).
+SEED_STRIDE = 100
+MAX_TEMPERATURES = 10
+
+
+def loop_seed(seed, k, a):
+    """Solver seed base of chemical-potential index k at temperature index a."""
+    return seed + 10 * SEED_STRIDE * k + SEED_STRIDE * a
+
+
+def _check_seed_room(max_iter, n_temperatures=1):
+    if max_iter > SEED_STRIDE:
+        raise ValueError(f"max_iter {max_iter} > {SEED_STRIDE}: loop seeds would overlap")
+    if n_temperatures > MAX_TEMPERATURES:
+        raise ValueError(f"more than {MAX_TEMPERATURES} temperatures: loop seeds would overlap")
+
 
 def staggered_magnetization(density, coords):
     """(-1)^(x + y) (n_up - n_dn) per site: density (sites, 2), coords (sites, 2)."""
@@ -20,7 +39,7 @@ def staggered_magnetization(density, coords):
     return np.where(c.sum(axis=1) % 2 == 0, 1.0, -1.0) * (d[:, 0] - d[:, 1])
 
 
-def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, sites, n_warmup, n_measure, seeds,
+def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, sites, n_warmup, n_measure, seed,
                  n_freq=500, tol=2e-3, max_iter=10, n_bins=16, warm_start=True, mu_group=1):
     """Converged densities at beta = L dtau for every L in Ls (several
     temperatures at a fixed dtau) and every chemical potential
@@ -31,14 +50,15 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
     from the self-energy converged at the last chemical potential of the
     group before (warm_start) or from the empty system.  eps_seed (with a seed
     field) is used for the first iteration at every mu, eps afterwards.  The
-    solver seed of (mu index k, temperature a) is seeds[a] + 1000 k whatever
-    the grouping.  Returns per L: densities (len(mus), len(sites), 2), errors
+    solver seed of (mu index k, temperature a) is loop_seed(seed, k, a), plus
+    the iteration index, whatever the grouping.  Returns per L: densities (len(mus), len(sites), 2), errors
     of n_up + n_dn (len(mus), len(sites)), iteration counts, the largest
     change of a spin density and of n_up + n_dn in each point's last
     iteration (len(mus), 2) (NaN after a single iteration); and the solver
     proposals of all iterations."""
     if mu_group < 1:
         raise ValueError("mu_group must be positive")
+    _check_seed_room(max_iter, len(Ls))
     N = lattice.n_sites
     empty = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
     sig = [empty] * len(Ls)
@@ -52,7 +72,7 @@ def density_scan(ctx, lattice, hop, layer, eps, eps_seed, U, mus, Ls, dtau, site
         keys = [(k, a) for k in ks for a in range(len(Ls))]
         loops = [RDMFT(ctx, hop, layer, eps_seed, mus[k], U, Ls[a] * dtau, Ls[a], n_freq=n_freq,
                        sigma0=sig[a] if warm_start else empty, lattice=lattice) for k, a in keys]
-        outs = converge_together(loops, sites, n_warmup, n_measure, [seeds[a] + 1000 * k for k, a in keys],
+        outs = converge_together(loops, sites, n_warmup, n_measure, [loop_seed(seed, k, a) for k, a in keys],
                                  tol=tol, max_iter=max_iter, eps_after=eps, n_bins=n_bins)
         for (k, a), r, o in zip(keys, loops, outs):
             dens[a][k] = o["density"]
@@ -97,7 +117,7 @@ def entropy_scan(ctx, hop, layer, eps, eps_seed, U, mus, L_lo, L_hi, dtau, sites
     try:
         (n_lo, n_hi), (e_lo, e_hi), (it_lo, it_hi), props, (c_lo, c_hi) = density_scan(
             ctx, lat, hop, layer, eps, eps_seed, U, mus, (L_hi, L_lo), dtau, sites, n_warmup, n_measure,
-            (seed, seed + 7), **kw)
+            seed, **kw)
     finally:
         lat.close()
     T_lo, T_hi = 1.0 / (L_hi * dtau), 1.0 / (L_lo * dtau)
@@ -114,6 +134,7 @@ def find_mu(ctx, hop, layer, eps, U, L, dtau, sites, target, mu_lo, mu_hi, n_war
     [mu_lo, mu_hi] (N grows with mu); each step is a converged RDMFT loop
     started from the nearest converged self-energy so far.  Returns
     dict(mu, atoms, steps: [(mu, atoms)])."""
+    _check_seed_room(max_iter)
     lat = hfqmc.Lattice(ctx, hop, layer)
     N = lat.n_sites
     beta = L * dtau
@@ -125,7 +146,7 @@ def find_mu(ctx, hop, layer, eps, U, L, dtau, sites, target, mu_lo, mu_hi, n_war
         else:
             sigma0 = np.full((2, n_freq, N), -0.5 * U, dtype=np.complex128)
         r = RDMFT(ctx, hop, layer, eps, mu, U, beta, L, n_freq=n_freq, sigma0=sigma0, lattice=lat)
-        out = r.converge(sites, n_warmup, n_measure, seed + len(seen), tol=tol, max_iter=max_iter, n_bins=n_bins)
+        out = r.converge(sites, n_warmup, n_measure, seed + SEED_STRIDE * len(seen), tol=tol, max_iter=max_iter, n_bins=n_bins)
         n = float(out["density"].sum())
         seen.append((mu, n, r.sigma.cpu().numpy()))
         r.close()

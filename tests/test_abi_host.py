@@ -196,3 +196,21 @@ def test_result_buffers_are_disjoint_and_read_back():
         assert (o["n_up"], o["n_dn"], o["proposals"], o["status"]) == (0.25 + i, 0.5 + i, 17 * i, -i)
         assert isinstance(o["proposals"], int) and isinstance(o["n_up"], float)
     assert hfqmc._Results([]).to_list() == []
+
+
+def test_scan_solver_seeds_never_repeat():
+    """Every (chemical potential, temperature, iteration) loop of an entropy
+    scan, and every bisection step of the chemical-potential search, draws a
+    solver seed of its own: the Philox key is (seed, site), so a repeated
+    seed would replay another loop's fields and uniforms."""
+    from paper_1006_2716_amd import thermo
+    max_iter, n_mu = thermo.SEED_STRIDE, 60
+    seeds = [thermo.loop_seed(5, k, a) + it for k in range(n_mu) for a in range(thermo.MAX_TEMPERATURES)
+             for it in range(max_iter)]
+    assert len(set(seeds)) == len(seeds)
+    steps = [5 + thermo.SEED_STRIDE * s + it for s in range(40) for it in range(max_iter)]
+    assert len(set(steps)) == len(steps)
+    with pytest.raises(ValueError):
+        thermo._check_seed_room(thermo.SEED_STRIDE + 1)
+    with pytest.raises(ValueError):
+        thermo._check_seed_room(5, thermo.MAX_TEMPERATURES + 1)

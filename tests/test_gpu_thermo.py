@@ -151,9 +151,9 @@ def test_grouped_scan_equals_one_mu_at_a_time(ctx):
     lat = hfqmc.Lattice(ctx, hop, 4)
     try:
         kw = dict(n_freq=100, tol=1e-12, max_iter=2, n_bins=4, warm_start=False)
-        one = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, (4, 11), **kw)
+        one = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, 4, **kw)
         print("grouped scan: 7 chemical potentials in groups of 3 (cold starts)", flush=True)
-        grp = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, (4, 11),
+        grp = density_scan(ctx, lat, hop, 4, plain, eps, 4.0, mus, (18, 22), 0.2, sites, 20, 200, 4,
                            mu_group=3, **kw)
     finally:
         lat.close()
@@ -165,4 +165,4 @@ def test_grouped_scan_equals_one_mu_at_a_time(ctx):
         assert np.all(np.isfinite(one[4][a])) and np.all(one[4][a] >= 0)
     assert one[3] == grp[3]
     with pytest.raises(ValueError):
-        density_scan(ctx, None, hop, 4, plain, eps, 4.0, mus, (18,), 0.2, sites, 1, 4, (1,), mu_group=0)
+        density_scan(ctx, None, hop, 4, plain, eps, 4.0, mus, (18,), 0.2, sites, 1, 4, 1, mu_group=0)

@@ -153,3 +153,38 @@ def test_sigma_of_the_atom_converges_to_the_closed_form():
         assert np.max(np.abs(sig[nc:] - exact[nc:]) * w[nc:] ** 2) < 3 * U ** 3
     assert errs[-1] < 2e-3
     assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_weiss_of_isolated_sites_is_the_bare_level_for_any_sigma():
+    """Without hopping G_loc = 1 / (iw + mu - eps - sigma), so the impurity
+    Dyson equation must give back 1 / (iw + mu - eps) whatever sigma is; a
+    sign slip (G^-1 - sigma) leaves 2 sigma behind."""
+    rng = np.random.default_rng(7)
+    N, beta, nf, mu = 5, 3.0, 6, 0.25
+    eps = rng.normal(size=(2, N))
+    sig = rng.normal(size=(2, nf, N)) - 1j * rng.uniform(0.2, 2.0, size=(2, nf, N))
+    gl = rd.lattice_local_green(np.zeros((N, N)), eps, mu, sig, beta)
+    w = rd.matsubara(beta, nf)
+    ref = 1.0 / (1j * w[None, :, None] + mu - eps[:, None, :])
+    assert np.max(np.abs(rd.weiss_iw(gl, sig) - ref)) < 1e-13
+
+
+def test_weiss_of_a_dimer_is_the_cavity_function():
+    """Two sites joined by hopping t: the 2x2 inverse gives
+    G_11 = z2 / (z1 z2 - t^2), z_i = iw + mu - eps_i - sigma_i, so the Weiss
+    function of site 1 is 1 / (iw + mu - eps_1 - t^2 / z2): the cavity
+    (hybridisation) form, independent of sigma_1 and depending on sigma_2."""
+    t, mu, beta, nf = 0.8, 0.1, 4.0, 5
+    eps = np.array([[0.3, -0.4], [0.5, 0.2]])
+    rng = np.random.default_rng(3)
+    sig = rng.normal(size=(2, nf, 2)) - 1j * rng.uniform(0.1, 1.5, size=(2, nf, 2))
+    hop = np.array([[0.0, -t], [-t, 0.0]])
+    gl = rd.lattice_local_green(hop, eps, mu, sig, beta)
+    wf = rd.weiss_iw(gl, sig)
+    iw = 1j * rd.matsubara(beta, nf)
+    for s in range(2):
+        z = iw[:, None] + mu - eps[s][None, :] - sig[s]
+        ref0 = 1.0 / (iw + mu - eps[s, 0] - t * t / z[:, 1])
+        ref1 = 1.0 / (iw + mu - eps[s, 1] - t * t / z[:, 0])
+        assert np.max(np.abs(wf[s, :, 0] - ref0)) < 1e-13
+        assert np.max(np.abs(wf[s, :, 1] - ref1)) < 1e-13
