@@ -50,14 +50,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 flop/clk/CU
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 flop/clk/CU (fp64 MFMA: the same)
+FP32_MFMA_PEAK_TFLOPS = 157.3
 RECOMPUTE_EVERY = 50
 
-# HBM bytes per launch of the sweep kernel on this workload, from rocprofv3
-# FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/sweep_kernel_L64x512_fp64.md),
-# valid only for the kernel source with this sha256 prefix.
-PROFILED_KERNEL_SHA = "94ccf9d89011127e"
-PROFILED_TRAFFIC_BYTES = 1.747e9
+# HBM bytes per launch of the dominant kernel on this workload, from
+# rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by a 256 MiB copy (profiles/),
+# valid only for the kernel sources with the sha256 prefix recorded with them.
+PROFILED_TRAFFIC = {
+    # kernel: (source files, sha256 prefix, bytes per launch)
+    "hfqmc::sweep_kernel<Cfg<64,2,0>>": (("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h"),
+                                         "94ccf9d89011127e", 1.747e9),
+}
 
 
 # lattice Green function kernel (21 x 21 trap, 500 frequencies x 2 spins):
@@ -76,8 +80,12 @@ def kernel_sha(files=("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h")) 
     return h.hexdigest()[:16]
 
 
-def kernel_traffic():
-    return PROFILED_TRAFFIC_BYTES if kernel_sha() == PROFILED_KERNEL_SHA else None
+def kernel_traffic(kernel: str):
+    ent = PROFILED_TRAFFIC.get(kernel)
+    if ent is None:
+        return None
+    files, sha, traffic = ent
+    return traffic if kernel_sha(files) == sha else None
 
 
 def lattice_traffic():
@@ -446,9 +454,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-single", action="store_true", help="skip the single-impurity comparison")
-    ap.add_argument("--delay", type=int, default=1,
-                    help="update depth: 1 rank-one (default, measured fastest), 2..32 delayed rank-k")
-    ap.add_argument("--mixed", action="store_true", help="fp32 delayed-update products (with --delay > 1)")
+    ap.add_argument("--delay", type=int, default=0,
+                    help="update kind: 0 window updates (default), 1 rank-one, 2..32 delayed rank-k")
+    ap.add_argument("--mixed", action="store_true", help="fp32 products in the window flush or the delayed updates")
     ap.add_argument("--graph", action="store_true", help="replay the pass from a captured hipGraph")
     ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
     ap.add_argument("--quantum", type=int, default=0, help="serving: fixed proposals per request per step")
@@ -529,15 +537,25 @@ def main():
     p_acc = accepts / proposals
     value = proposals / (ms_per_step * 1e-3)
 
+    window = k == 0
     kbar = 0.0 if k <= 1 else (k - 1) / 2.0  # mean pending updates while appending
     flops_launch = proposals * algorithmic_flops(L, p_acc, kbar=kbar)
     kavg = float(np.mean(kern_ms))
     achieved = flops_launch / (kavg * 1e-3) / 1e12
-    dk = 0 if k <= 1 else (2 if args.mixed else 1)
-    traffic = kernel_traffic() if (k <= 1 and not args.graph) else None
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), traffic=traffic,
-                    kernel=f"hfqmc::sweep_kernel<Cfg<64,{rt},{dk}>>", kernel_avg_ms=round(kavg, 4),
+    if window:
+        dk = 4 if args.mixed else 3
+        kname = f"hfqmc::window_kernel<WCfg<64,{rt},{1 if args.mixed else 0}>>"
+        # the window kernel's update flops run on the matrix cores: fp64 MFMA
+        # (78.6 TFLOP/s on MI355X, the same figure as the fp64 vector peak),
+        # fp32 MFMA when the flush forms fp32 products
+        bound, peak = "mfma", (FP32_MFMA_PEAK_TFLOPS if args.mixed else FP64_VECTOR_PEAK_TFLOPS)
+    else:
+        dk = 0 if k <= 1 else (2 if args.mixed else 1)
+        kname = f"hfqmc::sweep_kernel<Cfg<64,{rt},{dk}>>"
+        bound, peak = "alu", FP64_VECTOR_PEAK_TFLOPS
+    traffic = kernel_traffic(kname) if not args.graph else None
+    roofline = dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(achieved / peak, 4), traffic=traffic, kernel=kname, kernel_avg_ms=round(kavg, 4),
                     flops_per_launch=flops_launch)
 
     out = {
@@ -553,11 +571,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not args.mixed else "f64+f32 (delayed products)",
+        "dtype": "f64" if not args.mixed else "f64+f32 (update products)",
         "data": "synthetic",
         "config": {"workload": "512 impurities x L=64 (beta=8, dtau=0.125), U~U[4,12], open 64-site chain "
                                "centre-site Weiss at mu_eff~U[-1,1], 200+2000 sweeps, "
-                               + ("rank-one SM updates" if k <= 1 else f"delayed rank-{k} updates")
+                               + ("window updates (16 slices, MFMA flush)" if window else
+                                  ("rank-one SM updates" if k <= 1 else f"delayed rank-{k} updates"))
                                + (", fp32 products" if args.mixed else ", fp64"),
                    "n_impurities": n_imp, "L": L, "sweeps": 2200, "recompute_every": RECOMPUTE_EVERY,
                    "proposals_per_step": proposals, "accept_rate": round(p_acc, 4), "delay": k,

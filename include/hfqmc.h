@@ -90,7 +90,9 @@ typedef struct {
     uint64_t site_id;           /* Philox key word 1 */
     int64_t sweep_offset;       /* added to the sweep index in the Philox counter */
     const int8_t *init_fields;  /* host, L entries (+1/-1), or NULL to draw them */
-    int32_t delay;              /* 0: library choice (autotuned shape, else 1);
+    int32_t delay;              /* 0: library choice (the autotuned shape -- rank-one,
+                                   delayed or window updates -- else the untuned
+                                   default for L);
                                    1: rank-one Sherman-Morrison updates;
                                    2..32: delayed rank-k updates, flushed into G
                                    every k accepted flips (fp32 products when
@@ -177,8 +179,11 @@ hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx *ctx, int32_t i, double *ms, int32_t
 
 /* ---- autotuning (kernel shape per padded slice count) ----
  * For every padded L present in `problems`, time each compiled kernel shape
- * (tile-rows per wave; rank-one, or delayed with k in {4, 8, 16, 32} in the
- * context precision) on those problems shortened to `sweeps` sweeps (>= 4),
+ * (tile-rows per wave; window updates (k = 0: the decisions of 16 slices
+ * taken on the 16 x 16 diagonal blocks of G, then one rank-|accepted|
+ * matrix-core update of G), rank-one, or delayed with k in {4, 8, 16, 32};
+ * fp32 products in the context precision HFQMC_MIXED) on those problems
+ * shortened to `sweeps` sweeps (>= 4),
  * keep the fastest, and write the table to the context's tune cache (JSON,
  * if a path was given to hfqmc_create).  Problems with delay 0 then use the
  * tuned shape.  d_ws must hold hfqmc_workspace_size(problems); any staged
@@ -186,7 +191,7 @@ hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx *ctx, int32_t i, double *ms, int32_t
 hfqmc_status hfqmc_tune(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
                         int32_t sweeps);
 /* The shape a problem with L slices and this delay would run with:
- * tile-rows per wave, delay depth (1 = rank-one) and the tuned rate in
+ * tile-rows per wave, delay depth (1 = rank-one, 0 = window updates) and the tuned rate in
  * proposals/s (0 if untuned).  Pointers may be NULL. */
 hfqmc_status hfqmc_plan(hfqmc_ctx *ctx, int32_t L, int32_t delay, int32_t *rt, int32_t *k, double *tuned_rate);
 

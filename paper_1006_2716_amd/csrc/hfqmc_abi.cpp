@@ -87,10 +87,46 @@ constexpr int kSrvStreams = 6;   // serving launch streams
 constexpr int kMaxChains = 64;   // independent chains per problem
 
 // Kernel shape of one class: tile-rows per wave, update kind (0 plain
-// rank-one, 1 delayed fp64, 2 delayed mixed) and delay depth.
+// rank-one, 1 delayed fp64, 2 delayed mixed, 3 window updates, 4 window
+// updates with fp32 products), delay depth (0 for window updates) and the
+// kernel's padded slice count.
 struct Plan {
-  int rt = 1, dk = 0, k = 1;
+  int rt = 1, dk = 0, k = 1, LT = 16;
 };
+
+constexpr int kDkWindow = 3, kDkWindowMixed = 4;
+inline bool is_window(int dk) { return dk == kDkWindow || dk == kDkWindowMixed; }
+
+// Padded slice count of the window kernel serving L <= 128: the next
+// multiple of 16 up to 96, then 128 (no 112-slice window kernel is built:
+// seven tile-rows per wave do not fit the register file).
+int window_LT(int L) {
+  if (L <= 96) return (L + 15) / 16 * 16;
+  return 128;
+}
+
+// Padded slice count of the kernel of update kind dk for L slices.
+int kernel_LT(int L, int dk) { return is_window(dk) && L <= kMaxRegisterL ? window_LT(L) : (L + 15) / 16 * 16; }
+
+// Padded slice counts at which the untuned default is the window kernel
+// (elsewhere the rank-one kernel, measured faster there on MI355X).
+bool window_default(int LT) {
+  (void)LT;
+  return false;
+}
+
+// Untuned tile-rows per wave of the window kernels: the flush is spread over
+// as many waves as the register file allows two impurities per CU up to 80
+// slices, one beyond.
+int default_rt_window(int LT) {
+  switch (LT) {
+    case 64: return 2;
+    case 80: return 5;
+    case 96: return 3;
+    case 128: return 4;
+    default: return 1;
+  }
+}
 
 // Untuned default tile-rows per wave, each the measured best of the rank-one
 // kernels on MI355X: 2 at 64 (512 impurities: 76 ms against 103 with 1 and
@@ -110,7 +146,9 @@ int default_rt(int LT, int dk) {
 // (the drift snapshot of the device-memory kernel, the parked bin sums of G
 // of the register kernels), then 3 x 64 parked per-lane sums.
 size_t state_bytes(int L) {
-  const size_t LT = (size_t)((L + 15) / 16 * 16);
+  // large enough for every kernel that can run L slices (window kernels may
+  // pad further than the next multiple of 16)
+  const size_t LT = (size_t)(L <= kMaxRegisterL ? window_LT(L) : (L + 15) / 16 * 16);
   return sizeof(double) * (4 * LT * LT + 256);
 }
 
@@ -618,22 +656,27 @@ void pool_free(hfqmc_ctx* c, size_t off, size_t bytes) {
 }
 
 // Kernel shape for a problem: explicit delay, else the tuned entry of its
-// class, else the default plain kernel.
+// class, else the default window-update kernel.
 Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
   const int LT = padded_L(p.L);
   const int dk_delayed = c->prec == HFQMC_MIXED ? 2 : 1;
+  const int dk_window = c->prec == HFQMC_MIXED ? kDkWindowMixed : kDkWindow;
   Plan pl;
   auto it = c->tune.find(LT);
   const bool tuned = it != c->tune.end();
   if (p.delay == 0 && tuned) {
     pl.k = it->second.k;
     pl.rt = it->second.rt;
-    pl.dk = pl.rt == 0 ? 1 : (pl.k > 1 ? dk_delayed : 0);
+    pl.dk = pl.k == 0 ? dk_window : (pl.rt == 0 ? 1 : (pl.k > 1 ? dk_delayed : 0));
   } else if (LT > kMaxRegisterL) {
     // only the global-memory kernel (fp64 delayed updates) handles these
     pl.rt = 0;
     pl.dk = 1;
     pl.k = p.delay >= 1 ? p.delay : kGlobalMaxDelay;
+  } else if (p.delay == 0 && window_default(window_LT(p.L))) {
+    pl.dk = dk_window;
+    pl.k = 0;
+    pl.rt = default_rt_window(window_LT(p.L));
   } else if (p.delay <= 1) {
     pl.rt = tuned && it->second.k == 1 ? it->second.rt : default_rt(LT, 0);
   } else {
@@ -641,6 +684,7 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
     pl.dk = dk_delayed;
     pl.rt = tuned && it->second.k > 1 ? it->second.rt : default_rt(LT, pl.dk);
   }
+  pl.LT = kernel_LT(p.L, pl.dk);
   return pl;
 }
 
@@ -668,9 +712,10 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
   for (int i = 0; i < n; ++i) {
     idx[i] = i;
     plan[i] = force ? *force : plan_for(c, p[i]);
+    if (force) plan[i].LT = kernel_LT(p[i].L, plan[i].dk);
     if (plan[i].rt == 0 && plan[i].k > kGlobalMaxDelay)
       return fail(HFQMC_EINVAL, "problem %d: delay %d > %d for L=%d", ex.owner[i], plan[i].k, kGlobalMaxDelay, p[i].L);
-    if (!find_kernel(padded_L(p[i].L), plan[i].rt, plan[i].dk))
+    if (!find_kernel(plan[i].LT, plan[i].rt, plan[i].dk))
       return fail(HFQMC_EINVAL, "problem %d: no %s kernel for L=%d", ex.owner[i],
                   plan[i].dk ? "delayed-update" : "sweep", p[i].L);
   }
@@ -684,7 +729,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
     const double lam = coupling(p[i].beta / p[i].L, p[i].U);
     return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * std::max(p[i].L, 64) * std::exp(-0.76 * lam * lam);
   };
-  auto key = [&](int i) { return std::make_tuple(-padded_L(p[i].L), plan[i].dk, plan[i].rt); };
+  auto key = [&](int i) { return std::make_tuple(-plan[i].LT, plan[i].dk, plan[i].rt); };
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
     if (key(a) != key(b)) return key(a) < key(b);
     return cost(a) > cost(b);
@@ -693,8 +738,8 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
   for (int k = 0; k < n;) {
     int e = k;
     while (e < n && key(idx[e]) == key(idx[k])) ++e;
-    const int LT = padded_L(p[idx[k]].L);
     const Plan& pl = plan[idx[k]];
+    const int LT = pl.LT;
     const KernelInfo* ki = find_kernel(LT, pl.rt, pl.dk);
     int bpc = 0;
     HIP_TRY(kernel_occupancy(ki, &bpc));
@@ -711,7 +756,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
   for (int i = 0; i < n; ++i) {
     ImpDesc d{};
     fill_constants(d, p[i]);
-    d.LT = padded_L(p[i].L);
+    d.LT = plan[i].LT;
     d.op = OP_SWEEPS;
     d.delay = plan[i].k;
     d.flags = F_ZERO_ACC | (p[i].init_fields ? F_FIELDS_GIVEN : 0) | F_SAVE;
@@ -1173,10 +1218,15 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     c->tune_path = tune_cache;
     c->tune_all = read_tune_cache(c->tune_path);
     for (const auto& t : c->tune_all) {
+      if (t.prec != prec_name(precision)) continue;
+      if (t.k == 0) {  // window updates
+        const int dk = precision == HFQMC_MIXED ? kDkWindowMixed : kDkWindow;
+        if (t.LT <= kMaxRegisterL && find_kernel(window_LT(t.LT), t.rt, dk)) c->tune[t.LT] = t;
+        continue;
+      }
       const int dk = t.rt == 0 ? 1 : (t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0);
       const int kmax = t.rt == 0 ? kGlobalMaxDelay : kMaxDelay;
-      if (t.prec == prec_name(precision) && t.k >= 1 && t.k <= kmax && find_kernel(t.LT, t.rt, dk))
-        c->tune[t.LT] = t;
+      if (t.k >= 1 && t.k <= kmax && find_kernel(t.LT, t.rt, dk)) c->tune[t.LT] = t;
     }
   }
   *out = c;
@@ -1348,6 +1398,11 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
       }
     std::vector<Plan> cands;
     int rts[16];
+    if (LT <= kMaxRegisterL) {  // window updates (k = 0 in the cache)
+      const int dk_window = c->prec == HFQMC_MIXED ? kDkWindowMixed : kDkWindow;
+      const int nw = std::min(16, kernel_variants(window_LT(LT), dk_window, rts, 16));
+      for (int v = 0; v < nw; ++v) cands.push_back({rts[v], dk_window, 0});
+    }
     int nv = std::min(16, kernel_variants(LT, 0, rts, 16));
     for (int v = 0; v < nv; ++v) cands.push_back({rts[v], 0, 1});
     nv = std::min(16, kernel_variants(LT, dk_delayed, rts, 16));
@@ -1440,11 +1495,11 @@ hfqmc_status hfqmc_site_open(hfqmc_ctx* c, int32_t L, int32_t n_bins, int32_t n_
   hfqmc_site* s = new (std::nothrow) hfqmc_site;
   if (!s) return fail(HFQMC_ENOMEM, "out of host memory");
   s->L = L;
-  s->LT = padded_L(L);
   hfqmc_problem p{};
   p.L = L;
   p.delay = 0;
   const Plan pl = plan_for(c, p);
+  s->LT = pl.LT;
   s->RT = pl.rt;
   s->DK = pl.dk;
   s->K = pl.k;

@@ -183,14 +183,16 @@ struct SliceState {
 
 // One compiled sweep kernel.  RT = tile-rows per wave of the register-tile
 // kernels, 0 for the global-memory kernel; DK = update kind (0 rank-one,
-// 1 delayed fp64, 2 delayed with fp32 products).
+// 1 delayed fp64, 2 delayed with fp32 products, 3 window updates, 4 window
+// updates with fp32 products).
 struct KernelInfo {
   int LT, RT, DK, threads;
   size_t lds;
   const void* fn;
 };
 
-// Global-memory kernels of the other translation unit.
+// Kernels of the other translation units.
 int global_kernels(const KernelInfo** list);
+int window_kernels(const KernelInfo** list);
 
 }  // namespace hfqmc

@@ -749,32 +749,35 @@ static const KernelInfo kKernels[] = {
     info<32, 1, 2>(), info<48, 1, 2>(), info<64, 2, 2>(), info<80, 1, 2>(), info<96, 1, 2>(), info<128, 1, 2>(),
 };
 
-const KernelInfo* find_kernel(int LT, int RT, int DK) {
+// Every compiled kernel: the rank-one and delayed register kernels of this
+// unit, the window kernels and the global-memory kernels.
+template <class F>
+static const KernelInfo* each_kernel(F&& f) {
   for (const auto& k : kKernels)
-    if (k.LT == LT && k.RT == RT && k.DK == DK) return &k;
-  const KernelInfo* g = nullptr;
-  const int ng = global_kernels(&g);
-  for (int i = 0; i < ng; ++i)
-    if (g[i].LT == LT && g[i].RT == RT && g[i].DK == DK) return &g[i];
+    if (f(k)) return &k;
+  const KernelInfo* lists[2] = {nullptr, nullptr};
+  const int counts[2] = {window_kernels(&lists[0]), global_kernels(&lists[1])};
+  for (int l = 0; l < 2; ++l)
+    for (int i = 0; i < counts[l]; ++i)
+      if (f(lists[l][i])) return &lists[l][i];
   return nullptr;
+}
+
+const KernelInfo* find_kernel(int LT, int RT, int DK) {
+  return each_kernel([&](const KernelInfo& k) { return k.LT == LT && k.RT == RT && k.DK == DK; });
 }
 
 // Tile-rows-per-wave variants compiled for (LT, DK), 0 standing for the
 // global-memory kernel; returns their count.
 int kernel_variants(int LT, int DK, int* rt_out, int max) {
   int n = 0;
-  for (const auto& k : kKernels)
+  each_kernel([&](const KernelInfo& k) {
     if (k.LT == LT && k.DK == DK) {
       if (n < max) rt_out[n] = k.RT;
       ++n;
     }
-  const KernelInfo* g = nullptr;
-  const int ng = global_kernels(&g);
-  for (int i = 0; i < ng; ++i)
-    if (g[i].LT == LT && g[i].DK == DK) {
-      if (n < max) rt_out[n] = g[i].RT;
-      ++n;
-    }
+    return false;
+  });
   return n;
 }
 

@@ -1,0 +1,717 @@
+// hfqmc_window.h -- gfx950 sweep kernel with window (submatrix) updates.
+//
+// Same Hirsch-Fye chain as the rank-one register kernel: Metropolis test of
+// R = R_up R_dn, R_s = 1 + (1 - G_s[l][l]) d_s, d_s = exp(-2 s lambda s_l) - 1,
+// and on acceptance G_s += (d_s/R_s)(G_s[:,l] - e_l) G_s[l,:].  The slices of
+// a sweep are visited in windows W of 16 consecutive slices.  A decision in W
+// depends only on the diagonal of G, and a flip inside W changes the block
+// G[W,W] by a rank-one term built from G[W,W] itself, so every decision of a
+// window is taken on the two 16 x 16 blocks G_s[W,W] alone: one wave holds
+// them in registers and applies the rank-one updates there (no barrier, no
+// global column or row per accept).  The same wave accumulates
+// Q_s = prod_j (1 + u_j e_{l_j}^T) restricted to W, u_j the scaled window
+// column of accept j.  With S the accepted slices and D_s the diagonal of
+// their flip factors, the Hirsch-Fye relation G' = G + (G - 1)(e^{V'-V} - 1)G'
+// and G'[W,:] = Q G[W,:] give the update of the whole matrix at the window's
+// end as one rank-|S| product
+//     G_s += (G_s[:,S] - E_S) P_s G_s[S,:],   P_s = (D_s Q_s)[S,S],
+// which every wave applies to its register tiles with v_mfma_f64_16x16x4f64
+// (or, for fp32 products, v_mfma_f32_16x16x4f32 products added into the fp64
+// tiles).  The from-scratch Dyson solve G = [1 + (1 - G0)(e^V - 1)]^{-1} G0
+// uses the same windows, with every slice's potential switched on from V = 0
+// (factor exp(V_l) - 1) in place of a Metropolis decision.
+//
+// Layout: both G_s live in VGPRs as 16 x 16 tiles (lane = 16*(row/4) + col,
+// register = row % 4), wave w holding RT consecutive tile-rows of one spin,
+// exactly as the rank-one kernel, so the state area and its host readers are
+// shared.  Per window the owner of the window's tile-row publishes it in LDS
+// (double buffered), every wave stages its tiles of the window's column strip,
+// wave 0 scans, publishes P and S, and all waves flush: two barriers per
+// window instead of one per accepted flip.
+#pragma once
+#include "hfqmc_device.h"
+
+namespace hfqmc {
+
+template <int LT_, int RT_, int MX_ = 0>
+struct WCfg {
+  static constexpr int LT = LT_;            // padded slice count (multiple of 16)
+  static constexpr int RT = RT_;            // tile-rows per wave
+  static constexpr int MX = MX_;            // 1: fp32 products in the window flush
+  static constexpr int NT = LT / 16;        // tiles per dimension = windows per sweep
+  static constexpr int WPS = NT / RT;       // waves per spin
+  static constexpr int NW = 2 * WPS;        // waves per workgroup
+  static constexpr int NTH = 64 * NW;
+  static constexpr int JW = (LT + 63) / 64;  // 64-slice words of the field masks
+  static constexpr int RS = LT + 2;         // row stride of the published tile-row (doubles)
+  static constexpr int TS = 17;             // row stride of staged 16 x 16 tiles
+  static constexpr int GS = LT + 1;         // row stride of dumped rows (g(tau) estimator)
+  static constexpr int DR = LT < 64 ? LT : 64;  // rows per dump block
+  static constexpr int MINB = LT <= 64 ? 2 : 1;
+  static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
+  static_assert(NTH >= LT, "measurement needs one thread per tau_k");
+  static_assert(DR * GS <= 4 * 16 * RS, "dump block must fit the row buffers");
+};
+
+template <class C>
+struct WSmem {
+  union {
+    double rows[2][2][16 * C::RS];  // [buffer][spin]: the window's tile-row of G_s
+    double dump[C::DR * C::GS];     // a block of rows of one spin's G
+  } u;
+  double tb[C::NW][C::RT][16 * C::TS];  // each wave's tiles of the window's column strip
+  double pb[2][16 * C::TS];             // P_s = D_s Q_s of the window (window coordinates)
+  double diag[2][C::LT];                // diagonals of G_up, G_dn after a measured sweep
+  double weiss[2][C::LT];               // Weiss samples, zero padded
+  double red[C::NW];
+  uint32_t win[4];                      // S mask, |S|, accepted slices (4 bits each, two words)
+  int item;
+};
+
+typedef double wd4 __attribute__((ext_vector_type(4)));
+typedef float wf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double bperm_d(int addr, double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// a[k] for a per-lane k in [0, 4).  The array is taken by value: a select
+// of element addresses would turn register arrays into scratch memory.
+struct D4 {
+  double v[4];
+};
+__device__ __forceinline__ double sel4(D4 a, int k) {
+  const double x = (k & 1) ? a.v[1] : a.v[0];
+  const double y = (k & 1) ? a.v[3] : a.v[2];
+  return (k & 2) ? y : x;
+}
+__device__ __forceinline__ D4 d4of(const double (&a)[4]) { return D4{{a[0], a[1], a[2], a[3]}}; }
+
+enum WinMode : int {
+  WM_METROPOLIS = 0,  // Metropolis decisions over the window's slices
+  WM_DYSON = 1,       // switch every slice's potential on from V = 0
+  WM_FORCE = 2,       // flip one given slice
+};
+
+template <class C>
+struct EngineW {
+  static constexpr int LT = C::LT, RT = C::RT, NT = C::NT, JW = C::JW, RS = C::RS, TS = C::TS, GS = C::GS;
+
+  WSmem<C>& sm;
+  const int tid, wave, lane, spin, wr, q, c;
+  double g[RT][NT][4];                                // this wave's tiles of G_spin
+  uint64_t fm[JW];                                    // fields: bit set <=> s = -1 (uniform)
+  int buf = 0;                                        // row-buffer parity (uniform)
+  int L = 0;
+  ImpDesc d;
+  // wave-0 counters
+  int64_t accepts = 0, nonpos = 0, err = 0;
+
+  __device__ __forceinline__ EngineW(WSmem<C>& s)
+      : sm(s),
+        tid(threadIdx.x),
+        wave(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)),
+        lane(threadIdx.x & 63),
+        spin(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) / C::WPS),
+        wr(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % C::WPS),
+        q((threadIdx.x & 63) >> 4),
+        c(threadIdx.x & 15) {}
+
+  template <class F>
+  __device__ __forceinline__ void for_tiles(F&& f) {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        static_for<4>([&](auto r) __attribute__((always_inline)) { f(rt, tj, r); });
+      });
+    });
+  }
+
+  __device__ __forceinline__ int field_neg(int m) const {
+    const uint64_t w = pick<JW>(fm, m >> 6);
+    return (int)((w >> (m & 63)) & 1);
+  }
+
+  // ---------------------------------------------------------------- window
+  // Owner of tile-row ww of this wave's spin: publish it (all NT tiles).
+  __device__ __forceinline__ void publish_rows(int ww, int b) {
+    if (ww / RT != wr) return;
+    double* dst = sm.u.rows[b][spin] + (4 * q) * RS + c;
+    dispatch<RT>(ww % RT, [&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        static_for<4>([&](auto r) __attribute__((always_inline)) {
+          dst[r * RS + 16 * tj] = g[decltype(rt)::value][tj][r];
+        });
+      });
+      __asm__ volatile("" ::: "memory");
+    });
+  }
+
+  // Every wave: its tiles of column strip ww, row-major 16 x TS each.
+  __device__ __forceinline__ void stage_cols(int ww) {
+    dispatch<NT>(ww, [&](auto tj) __attribute__((always_inline)) {
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        double* dst = sm.tb[wave][rt] + (4 * q) * TS + c;
+        static_for<4>([&](auto r) __attribute__((always_inline)) { dst[r * TS] = g[rt][decltype(tj)::value][r]; });
+      });
+      __asm__ volatile("" ::: "memory");
+    });
+  }
+
+  // Rank-one update of both window blocks and of Q for an accepted slice j
+  // with factors f_s: u_s = f_s (B_s[:,j] - e_j), B_s += u_s B_s[j,:],
+  // Q_s += u_s Q_s[j,:].  Column j comes from lane 16q + j, row j from lane
+  // 16(j/4) + c, register j % 4.
+  __device__ __forceinline__ void rank1(int j, double fu, double fd, double (&bu)[4], double (&bd)[4],
+                                        double (&qu)[4], double (&qd)[4]) {
+    const int src_col = ((lane & 48) | j) << 2;
+    const int src_row = (((j & 12) << 2) | c) << 2;
+    const int jr = j & 3;
+    double cu[4], cd[4];
+    static_for<4>([&](auto r) __attribute__((always_inline)) {
+      cu[r] = bperm_d(src_col, bu[r]);
+      cd[r] = bperm_d(src_col, bd[r]);
+    });
+    const double rbu = bperm_d(src_row, sel4(d4of(bu), jr)), rbd = bperm_d(src_row, sel4(d4of(bd), jr));
+    const double rqu = bperm_d(src_row, sel4(d4of(qu), jr)), rqd = bperm_d(src_row, sel4(d4of(qd), jr));
+    static_for<4>([&](auto r) __attribute__((always_inline)) {
+      const double e = (4 * q + r == j) ? 1.0 : 0.0;
+      const double au = fu * (cu[r] - e), ad = fd * (cd[r] - e);
+      bu[r] = __builtin_fma(au, rbu, bu[r]);
+      bd[r] = __builtin_fma(ad, rbd, bd[r]);
+      qu[r] = __builtin_fma(au, rqu, qu[r]);
+      qd[r] = __builtin_fma(ad, rqd, qd[r]);
+    });
+  }
+
+  // Wave 0: the window's decisions.  Lane (q, c) with q == c/4 is the
+  // diagonal lane of window slice c (it holds G_s[c][c] in register c % 4).
+  // Writes P_s (window coordinates) and S to LDS.
+  __device__ __forceinline__ void scan(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out,
+                                       int b) {
+    const int base = 16 * ww;
+    double bu[4], bd[4], qu[4], qd[4];
+    {
+      const double* ru = sm.u.rows[b][0] + (4 * q) * RS + base + c;
+      const double* rd = sm.u.rows[b][1] + (4 * q) * RS + base + c;
+      static_for<4>([&](auto r) __attribute__((always_inline)) {
+        bu[r] = ru[r * RS];
+        bd[r] = rd[r * RS];
+        qu[r] = qd[r] = (4 * q + r == c) ? 1.0 : 0.0;
+      });
+    }
+    const uint32_t fw0 = (uint32_t)(pick<JW>(fm, base >> 6) >> (base & 63)) & 0xFFFFu;
+    const bool dl = q == (c >> 2);
+    const int rr = c & 3;
+    const bool in = base + c < L;
+    // factors as values: a conditional over the descriptor's members would
+    // select their addresses and keep the whole engine in scratch memory
+    const double fa = mode == WM_DYSON ? +d.dset_p : +d.dflip_p;  // sigma s_l = +1
+    const double fb = mode == WM_DYSON ? +d.dset_m : +d.dflip_m;  // sigma s_l = -1
+    const int sn = (fw0 >> c) & 1;
+    const double du = sn ? fb : fa, dd = sn ? fa : fb;
+    double u = 0.0;
+    if (mode == WM_METROPOLIS) u = bperm_d(((base + c) & 63) << 2, u01(pick<JW>(xw, ww >> 2)));
+    uint32_t S = 0;
+    int l0 = 0;
+    for (;;) {
+      const double Ru = __builtin_fma(1.0 - sel4(d4of(bu), rr), du, 1.0);
+      const double Rd = __builtin_fma(1.0 - sel4(d4of(bd), rr), dd, 1.0);
+      const double R = Ru * Rd;
+      const bool live = dl && in && c >= l0 && (mode != WM_FORCE || c == jf);
+      const uint64_t acc = __ballot(live && (mode != WM_METROPOLIS || u < R));
+      const double Fu = du * recip(Ru), Fd = dd * recip(Rd);
+      if (mode == WM_METROPOLIS) {
+        const uint64_t bad = __ballot(live && !(R > 0.0));
+        const uint64_t below = acc ? ((1ull << __builtin_ctzll(acc)) - 1) : ~0ull;
+        nonpos += __builtin_popcountll(bad & below);
+        if (bad & below) err = 1;
+      }
+      if (!acc) break;
+      const int lj = __builtin_ctzll(acc), j = lj & 15;
+      const double fu = readlane_d(Fu, lj), fd = readlane_d(Fd, lj);
+      if (mode == WM_FORCE) {
+        const double rv = readlane_d(R, lj);
+        if (lane == 0 && ratio_out) *ratio_out = rv;
+      }
+      rank1(j, fu, fd, bu, bd, qu, qd);
+      S |= 1u << j;
+      l0 = j + 1;
+    }
+    // P_s = D_s Q_s: row i scaled by the factor of slice i if accepted, else 0
+    double* pu = sm.pb[0] + (4 * q) * TS + c;
+    double* pd = sm.pb[1] + (4 * q) * TS + c;
+    static_for<4>([&](auto r) __attribute__((always_inline)) {
+      const int i = 4 * q + r;
+      const int si = (fw0 >> i) & 1;
+      const bool acc_i = (S >> i) & 1;
+      const double fu_i = si ? fb : fa, fd_i = si ? fa : fb;
+      pu[r * TS] = acc_i ? fu_i * qu[r] : 0.0;
+      pd[r * TS] = acc_i ? fd_i * qd[r] : 0.0;
+    });
+    uint64_t slist = 0;
+    int m = 0;
+    for (uint32_t t = S; t; t &= t - 1, ++m) slist |= (uint64_t)__builtin_ctz(t) << (4 * m);
+    if (mode == WM_METROPOLIS) accepts += m;
+    if (lane == 0) {
+      sm.win[0] = S;
+      sm.win[1] = (uint32_t)m;
+      sm.win[2] = (uint32_t)slist;
+      sm.win[3] = (uint32_t)(slist >> 32);
+    }
+  }
+
+  // Every wave: G_s += (G_s[:,S] - E_S) P_s[S,S] G_s[S,:] on its tiles.
+  // Per tile-row r: V = P^T (G[r-rows, S] - E)^T (16 x 16, rows = accepted
+  // slices in order, columns = the tile's rows permuted so that the update's
+  // fp64 accumulator lands in the tile layout), then for every tile column
+  // G[r, tj] += V^T G[S, tj]: the accumulator registers of V are the A
+  // operands of the update, four accepted slices per instruction.
+  template <bool FP32>
+  __device__ __forceinline__ void flush(int ww, int m, uint64_t slist, int b) {
+    const int K4 = (m + 3) >> 2;
+    const int ii = lane & 15, qq = lane >> 4;
+    const double* pb = sm.pb[spin];
+    const double* rows = sm.u.rows[b][spin];
+    const int si = (int)(slist >> (4 * ii)) & 15;
+    int sk[4];
+    bool kv[4];
+    static_for<4>([&](auto gi) __attribute__((always_inline)) {
+      const int k = 4 * gi + qq;
+      kv[gi] = k < m;
+      sk[gi] = (int)(slist >> (4 * k)) & 15;
+    });
+    // row of the tile fed as V's column ii: permuted for the fp64
+    // accumulator (rows 4*reg + lane/16), natural for fp32 (rows 4*(lane/16) + reg)
+    const int pi = FP32 ? ii : 4 * (ii & 3) + (ii >> 2);
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      const int r = wr * RT + rt;
+      wd4 V = {0.0, 0.0, 0.0, 0.0};
+      const double* tb = sm.tb[wave][rt];
+      static_for<4>([&](auto gi) __attribute__((always_inline)) {
+        if (gi < K4) {
+          const double a = (kv[gi] && ii < m) ? pb[sk[gi] * TS + si] : 0.0;
+          double bv = 0.0;
+          if (kv[gi]) {
+            bv = tb[pi * TS + sk[gi]];
+            if (r == ww && pi == sk[gi]) bv -= 1.0;
+          }
+          V = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, V, 0, 0, 0);
+        }
+      });
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        if constexpr (!FP32) {
+          wd4 acc = {g[rt][tj][0], g[rt][tj][1], g[rt][tj][2], g[rt][tj][3]};
+          static_for<4>([&](auto gi) __attribute__((always_inline)) {
+            if (gi < K4) {
+              const double bv = kv[gi] ? rows[sk[gi] * RS + 16 * tj + ii] : 0.0;
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(V[decltype(gi)::value], bv, acc, 0, 0, 0);
+            }
+          });
+          static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] = acc[decltype(r2)::value]; });
+        } else {
+          // fp32 products of four accepted slices each, added into the fp64 tile
+          static_for<4>([&](auto gi) __attribute__((always_inline)) {
+            if (gi < K4) {
+              const float bv = kv[gi] ? (float)rows[sk[gi] * RS + 16 * tj + ii] : 0.f;
+              wf4 p = {0.f, 0.f, 0.f, 0.f};
+              p = __builtin_amdgcn_mfma_f32_16x16x4f32((float)V[decltype(gi)::value], bv, p, 0, 0, 0);
+              static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] += (double)p[decltype(r2)::value]; });
+            }
+          });
+        }
+      });
+    });
+  }
+
+  // One window on every wave.  Returns the accepted slice mask.
+  __device__ __forceinline__ uint32_t window(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out) {
+    const int b = buf;
+    buf ^= 1;
+    publish_rows(ww, b);
+    stage_cols(ww);
+    __syncthreads();
+    if (wave == 0) scan(ww, mode, jf, xw, ratio_out, b);
+    __syncthreads();
+    const uint32_t S = __builtin_amdgcn_readfirstlane(sm.win[0]);
+    const int m = __builtin_amdgcn_readfirstlane(sm.win[1]);
+    const uint64_t slist = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sm.win[2]) |
+                           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sm.win[3]) << 32);
+    if (mode != WM_DYSON && S) {
+      const int base = 16 * ww;
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+        if (jj == (base >> 6)) fm[jj] ^= (uint64_t)S << (base & 63);
+      });
+    }
+    if (m) {
+      if (C::MX && mode == WM_METROPOLIS)
+        flush<true>(ww, m, slist, b);
+      else
+        flush<false>(ww, m, slist, b);
+    }
+    return S;
+  }
+
+  // ---------------------------------------------------------------- measurement
+  // Sum over rows i in [r0, r0 + nr) of eps G[i][(i - k) mod L] for the
+  // dumped rows (row i at (i - r0) * GS): the part of S_k = sum_l eps
+  // G[(l + k) mod L][l] (eps = -1 where l + k wraps) held by the block.
+  __device__ __forceinline__ double diag_block(const double* m, int k, int r0, int nr) const {
+    double a0 = 0.0, a1 = 0.0;
+    const int r1 = r0 + nr < L ? r0 + nr : L;
+    int i = r0;
+    // rows i < k wrap (l = i - k + L, eps = -1), rows i >= k do not
+    const int split = k < r0 ? r0 : (k < r1 ? k : r1);
+    for (; i + 2 <= split; i += 2) {
+      a0 -= m[(i - r0) * GS + i - k + L];
+      a1 -= m[(i + 1 - r0) * GS + i + 1 - k + L];
+    }
+    for (; i < split; ++i) a0 -= m[(i - r0) * GS + i - k + L];
+    for (; i + 2 <= r1; i += 2) {
+      a0 += m[(i - r0) * GS + i - k];
+      a1 += m[(i + 1 - r0) * GS + i + 1 - k];
+    }
+    for (; i < r1; ++i) a0 += m[(i - r0) * GS + i - k];
+    return a0 + a1;
+  }
+
+  // Write rows [r0, r0 + DR) of this wave's tiles into the dump.
+  __device__ __forceinline__ void dump_rows(int r0) {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      const int row0 = (wr * RT + rt) * 16;
+      if (row0 >= r0 && row0 < r0 + C::DR) {
+        double* dst = sm.u.dump + (row0 - r0 + 4 * q) * GS + c;
+        static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+          static_for<4>([&](auto r) __attribute__((always_inline)) { dst[r * GS + 16 * tj] = g[rt][tj][r]; });
+        });
+      }
+    });
+  }
+
+  // S_k of G_up and G_dn for thread k < L (other threads get 0).  The rows
+  // buffers are reused for the dump, one spin and DR rows at a time.
+  __device__ __forceinline__ void green_sums(double& su_k, double& sd_k) {
+    su_k = sd_k = 0.0;
+    static_for<2>([&](auto s) __attribute__((always_inline)) {
+      for (int r0 = 0; r0 < L; r0 += C::DR) {
+        __syncthreads();
+        if (spin == s) dump_rows(r0);
+        __syncthreads();
+        if (tid < L) (s == 0 ? su_k : sd_k) += diag_block(sm.u.dump, tid, r0, C::DR);
+      }
+    });
+    __syncthreads();
+  }
+
+  // Diagonal entries of this wave's diagonal tiles into sm.diag.
+  __device__ __forceinline__ void write_diag() {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        if (tj == wr * RT + rt && q == (c >> 2)) sm.diag[spin][16 * tj + c] = sel4(d4of(g[rt][tj]), c & 3);
+      });
+    });
+  }
+
+  // G = G0: the antiperiodic Toeplitz matrix of this wave's spin
+  // (G0[i][j] = g(tau_{i-j}) for i >= j, -g(tau_{i-j+L}) below), zero in the
+  // padding.
+  __device__ __forceinline__ void set_weiss() {
+    for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+      const int i = (wr * RT + rt) * 16 + 4 * q + r, j = tj * 16 + c;
+      double v = 0.0;
+      if (i < L && j < L) v = i >= j ? sm.weiss[spin][i - j] : -sm.weiss[spin][i - j + L];
+      g[rt][tj][r] = v;
+    });
+  }
+
+  // Largest |a - G| over this wave's diagonal tiles, a their earlier copy,
+  // reduced over the workgroup.
+  __device__ __forceinline__ void copy_diag_tiles(double (&a)[RT][4]) const {
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        if (tj == wr * RT + rt)
+          static_for<4>([&](auto r) __attribute__((always_inline)) { a[rt][r] = g[rt][tj][r]; });
+      });
+    });
+  }
+  __device__ __forceinline__ double diag_tile_drift(const double (&a)[RT][4]) {
+    double dr = 0.0;
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        if (tj == wr * RT + rt)
+          static_for<4>([&](auto r) __attribute__((always_inline)) { dr = fmax(dr, fabs(a[rt][r] - g[rt][tj][r])); });
+      });
+    });
+    dr = wave_max(dr);
+    if (lane == 0) sm.red[wave] = dr;
+    __syncthreads();
+    dr = 0.0;
+    for (int w = 0; w < C::NW; ++w) dr = fmax(dr, sm.red[w]);
+    __syncthreads();
+    return dr;
+  }
+
+  __device__ __forceinline__ double* state_ptr(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + (size_t)tid * (RT * NT * 4);
+  }
+  __device__ __forceinline__ double* lsum_state(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + 4 * (size_t)LT * LT;
+  }
+
+  // ---------------------------------------------------------------- item
+  // Every window of the item runs from one call site: passes are either a
+  // Dyson solve from G0 (first, after every recompute_every sweeps, or the
+  // OP_RECOMPUTE item), a Metropolis sweep, or one forced flip (OP_FORCE).
+  __device__ __forceinline__ void run(const ImpDesc* desc, uint8_t* ws) {
+    d = *desc;
+    L = d.L;
+    accepts = nonpos = err = 0;
+    buf = 0;
+    const int flags = d.flags;
+    const int NV = n_values(L);
+    double* bins = reinterpret_cast<double*>(ws + d.off_bins);
+    ImpStatus* st = reinterpret_cast<ImpStatus*>(ws + d.off_status);
+    int8_t* fields = reinterpret_cast<int8_t*>(ws + d.off_fields);
+    const double* wv = reinterpret_cast<const double*>(ws + d.off_weiss);
+    const int32_t* fslices = reinterpret_cast<const int32_t*>(ws + d.off_force);
+    double* fratios = reinterpret_cast<double*>(ws + d.off_force + 4 * ((d.n_force + 1) & ~1));
+
+    if (flags & F_ZERO_ACC) {
+      for (int i = tid; i < d.n_bins * NV; i += C::NTH) bins[i] = 0.0;
+      if (tid == 0) {
+        st->proposals = st->accepts = st->nonpositive = st->error = 0;
+        st->max_drift = 0.0;
+      }
+    }
+    for (int i = tid; i < 2 * LT; i += C::NTH) {
+      const int s = i / LT, k = i % LT;
+      sm.weiss[s][k] = k < L ? wv[s * L + k] : 0.0;
+    }
+    // fields as uniform bit masks
+    if (flags & (F_FIELDS_GIVEN | F_RESUME | F_KEEP_FIELDS)) {
+      const int8_t* fin = (flags & F_FIELDS_GIVEN) ? reinterpret_cast<const int8_t*>(ws + d.off_init) : fields;
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+        const int m = lane + 64 * jj;
+        fm[jj] = __ballot(m < L && fin[m] < 0);
+      });
+    } else {
+      const U64x4 x = philox4x64_10((uint64_t)lane, 0, kPurposeInit, (uint64_t)d.chain, d.seed, d.site);
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+        const int m = lane + 64 * jj;
+        fm[jj] = __ballot(m < L && (x.v[jj] >> 63));
+      });
+    }
+    if (flags & F_RESUME) {
+      const double* p = state_ptr(ws);
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+        g[rt][tj][r] = p[(rt * NT + tj) * 4 + r];
+      });
+    }
+    __syncthreads();
+
+    const bool sweeps = d.op == OP_SWEEPS;
+    const int64_t nm = d.n_measure, nb = d.n_bins;
+    double su = 0.0, sd = 0.0, sx = 0.0;  // wave 0: per-lane sums of 1-G_up, 1-G_dn and their product
+    double gau = 0.0, gad = 0.0;          // thread k < L: running bin sums of g_up(tau_k), g_dn(tau_k)
+    int64_t cur_bin = -1;
+    if (sweeps) {
+      const int64_t m0 = d.sweep_begin - d.n_warmup;
+      const bool cont = (flags & F_RESUME) && m0 > 0 && m0 < nm && (m0 * nb) / nm == ((m0 - 1) * nb) / nm;
+      if (cont && wave == 0) {
+        const double* la = lsum_state(ws);
+        su = la[lane];
+        sd = la[64 + lane];
+        sx = la[128 + lane];
+      }
+    }
+    int64_t proposals = 0;
+    double max_drift = 0.0;
+    int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+
+    // pass state
+    int64_t w = d.sweep_begin;  // sweep of the next Metropolis pass
+    int kf = 0;                 // next forced flip
+    int mode = (flags & F_RESUME) ? WM_METROPOLIS : WM_DYSON;
+    bool drift = false;         // the Dyson pass measures the drift
+    bool measure_after = false; // a measurement of sweep w - 1 follows the Dyson pass
+    if (d.op == OP_RECOMPUTE) {
+      mode = WM_DYSON;
+      drift = (flags & F_RESUME) != 0;
+    }
+    double dt[RT][4] = {};
+    for (;;) {
+      // ---- choose the pass
+      if (mode == WM_METROPOLIS) {
+        if (d.op == OP_FORCE) {
+          if (kf >= d.n_force) break;
+          mode = WM_FORCE;
+        } else if (!sweeps || w >= d.sweep_end) {
+          break;
+        }
+      }
+      int ww0 = 0, ww1 = (L + 15) >> 4, jf = 0;
+      double* rout = nullptr;
+      uint64_t xw[JW];
+      static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = 0; });
+      if (mode == WM_DYSON) {
+        if (drift) copy_diag_tiles(dt);
+        set_weiss();
+      } else if (mode == WM_FORCE) {
+        const int l = fslices[kf];
+        ww0 = l >> 4;
+        ww1 = ww0 + 1;
+        jf = l & 15;
+        rout = fratios + kf;
+      } else if (wave == 0) {
+        const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
+                                      (uint64_t)d.chain, d.seed, d.site);
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = x.v[jj]; });
+      }
+      // ---- the pass's windows
+      for (int ww = ww0; ww < ww1; ++ww) window(ww, mode, jf, xw, rout);
+      // ---- after the pass
+      bool measure = false;
+      if (mode == WM_DYSON) {
+        if (drift) max_drift = fmax(max_drift, diag_tile_drift(dt));
+        if (d.op == OP_RECOMPUTE) break;
+        measure = measure_after;
+        measure_after = false;
+        mode = WM_METROPOLIS;
+      } else if (mode == WM_FORCE) {
+        ++kf;
+        mode = WM_METROPOLIS;
+      } else {
+        proposals += L;
+        ++w;
+        if (w - 1 == next_rec) {  // recompute first, then measure sweep w - 1
+          next_rec += d.recompute_every;
+          mode = WM_DYSON;
+          drift = true;
+          measure_after = true;
+        } else {
+          measure = true;
+        }
+      }
+      if (!measure || w - 1 < d.n_warmup) continue;
+      // ---- measurement of sweep w - 1
+      const int64_t m = w - 1 - d.n_warmup;
+      const int64_t b = (m * nb) / nm;
+      double* bp = bins + (size_t)b * NV;
+      if (b != cur_bin) {
+        gau = tid < L ? bp[tid] : 0.0;
+        gad = tid < L ? bp[L + 1 + tid] : 0.0;
+        cur_bin = b;
+      }
+      {
+        double xu, xd;
+        green_sums(xu, xd);
+        gau += xu / (double)L;
+        gad += xd / (double)L;
+      }
+      write_diag();
+      __syncthreads();
+      if (wave == 0) {
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+          const int mm = lane + 64 * jj;
+          if (mm < L) {
+            const double xu = 1.0 - sm.diag[0][mm], xd = 1.0 - sm.diag[1][mm];
+            su += xu;
+            sd += xd;
+            sx += xu * xd;
+          }
+        });
+      }
+      if ((m + 1 == nm) || (((m + 1) * nb) / nm != b)) {  // the bin is complete
+        if (tid < L) {
+          bp[tid] = gau;
+          bp[L + 1 + tid] = gad;
+        }
+        cur_bin = -1;
+        if (wave == 0) {
+          const double nu = wave_sum(su) / (double)L, nd = wave_sum(sd) / (double)L;
+          const double dx = wave_sum(sx) / (double)L;
+          if (lane == 0) {
+            bp[L] = nu;
+            bp[2 * L + 1] = nd;
+            bp[2 * L + 2] = nu;
+            bp[2 * L + 3] = nd;
+            bp[2 * L + 4] = dx;
+          }
+        }
+        su = sd = sx = 0.0;
+      }
+    }
+    if (sweeps) {
+      // a bin still open when this launch ends: park its running sums
+      const int64_t ml = d.sweep_end - 1 - d.n_warmup;
+      if (d.sweep_end > d.sweep_begin && ml >= 0 && ml + 1 < nm && ((ml + 1) * nb) / nm == (ml * nb) / nm) {
+        double* bp = bins + (size_t)((ml * nb) / nm) * NV;
+        if (tid < L) {
+          bp[tid] = gau;
+          bp[L + 1 + tid] = gad;
+        }
+        if (wave == 0) {
+          double* la = lsum_state(ws);
+          la[lane] = su;
+          la[64 + lane] = sd;
+          la[128 + lane] = sx;
+        }
+      }
+    }
+
+    if (flags & F_SAVE) {
+      double* p = state_ptr(ws);
+      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+        p[(rt * NT + tj) * 4 + r] = g[rt][tj][r];
+      });
+      if (wave == 0) {
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+          const int m = lane + 64 * jj;
+          if (m < L) fields[m] = ((fm[jj] >> lane) & 1) ? (int8_t)-1 : (int8_t)1;
+        });
+      }
+    }
+    if (tid == 0) {
+      st->proposals += proposals;
+      st->accepts += accepts;
+      st->nonpositive += nonpos;
+      st->error |= err;
+      st->max_drift = fmax(st->max_drift, max_drift);
+    }
+    __syncthreads();
+  }
+};
+
+template <class C>
+__global__ __launch_bounds__(C::NTH, C::MINB) void window_kernel(const ImpDesc* __restrict__ descs,
+                                                                const int32_t* __restrict__ order, int n_items,
+                                                                int* __restrict__ queue, uint8_t* __restrict__ ws) {
+  __shared__ WSmem<C> sm;
+  EngineW<C> e(sm);
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = sm.item;
+    __syncthreads();
+    if (it >= n_items) break;
+    e.run(descs + order[it], ws);
+  }
+}
+
+// Update kinds of the window kernels in the kernel registry.
+constexpr int kDkWindow = 3, kDkWindowMixed = 4;
+
+template <int LT, int RT, int MX = 0>
+static KernelInfo winfo() {
+  using C = WCfg<LT, RT, MX>;
+  return KernelInfo{LT, RT, MX ? kDkWindowMixed : kDkWindow, C::NTH, sizeof(WSmem<C>),
+                    reinterpret_cast<const void*>(&window_kernel<C>)};
+}
+
+// Window kernels compiled in each translation unit (split for parallel builds).
+int window_kernels_fp64(const KernelInfo** list);
+int window_kernels_mixed(const KernelInfo** list);
+
+}  // namespace hfqmc

@@ -111,7 +111,7 @@ def test_autotuner_picks_measured_shape_and_persists(tmp_path):
         ents = {e["L_padded"]: e for e in data["entries"] if e["precision"] == "fp64"}
         assert set(ents) == {32, 48, 64}
         for LT, e in ents.items():
-            assert e["k"] in (1, 4, 8, 16, 32) and e["proposals_per_s"] > 0
+            assert e["k"] in (0, 1, 4, 8, 16, 32) and e["proposals_per_s"] > 0
             rt, k, rate = c.plan(LT, 0)
             assert (rt, k) == (e["rt"], e["k"]) and rate > 0
         # a new context reads the same plan from the cache

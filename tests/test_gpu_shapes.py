@@ -1,6 +1,7 @@
-"""Every compiled rank-one kernel shape (tile rows per wave) reproduces the
-oracle's Markov chain: each is forced through a tuning-cache entry and run on
-impurities whose L pads to its class, ragged tails included."""
+"""Every compiled kernel shape (tile rows per wave) of the rank-one and the
+window-update kernels reproduces the oracle's Markov chain: each is forced
+through a tuning-cache entry (k = 1: rank-one, k = 0: window updates) and run
+on impurities whose L pads to its class, ragged tails included."""
 import json
 
 import numpy as np
@@ -11,8 +12,11 @@ from paper_1006_2716_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 1), (32, 1), (32, 2), (48, 1), (48, 3), (64, 1), (64, 2), (64, 4), (80, 1), (96, 1), (96, 2),
-          (96, 3), (112, 1), (128, 1), (128, 2)]
+SHAPES = [(16, 1, 1), (32, 1, 1), (32, 2, 1), (48, 1, 1), (48, 3, 1), (64, 1, 1), (64, 2, 1), (64, 4, 1),
+          (80, 1, 1), (96, 1, 1), (96, 2, 1), (96, 3, 1), (112, 1, 1), (128, 1, 1), (128, 2, 1),
+          # window updates; the 112-slice class runs on the 128-slice window kernel
+          (16, 1, 0), (32, 1, 0), (32, 2, 0), (48, 1, 0), (48, 3, 0), (64, 1, 0), (64, 2, 0), (80, 5, 0),
+          (96, 3, 0), (112, 4, 0), (128, 4, 0)]
 
 
 def _problems(LT):
@@ -26,16 +30,16 @@ def _problems(LT):
     return out
 
 
-@pytest.mark.parametrize("LT,rt", SHAPES)
-def test_forced_shape_matches_oracle(tmp_path, LT, rt):
+@pytest.mark.parametrize("LT,rt,k", SHAPES)
+def test_forced_shape_matches_oracle(tmp_path, LT, rt, k):
     from paper_1006_2716_amd import hfqmc
-    print(f"shape LT={LT} rt={rt}", flush=True)
+    print(f"shape LT={LT} rt={rt} k={k}", flush=True)
     cache = tmp_path / "tune.json"
     cache.write_text(json.dumps({"arch": "gfx950", "entries": [
-        {"precision": "fp64", "L_padded": LT, "rt": rt, "k": 1, "proposals_per_s": 1.0}]}))
+        {"precision": "fp64", "L_padded": LT, "rt": rt, "k": k, "proposals_per_s": 1.0}]}))
     ctx = hfqmc.Context(0, tune_cache=str(cache))
     try:
-        assert ctx.plan(LT, 0)[:2] == (rt, 1)
+        assert ctx.plan(LT, 0)[:2] == (rt, k)
         probs = _problems(LT)
         gpu = ctx.solve(probs)
     finally:
