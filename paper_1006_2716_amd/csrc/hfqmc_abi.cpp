@@ -79,6 +79,7 @@ hfqmc_status fail(hfqmc_status s, const char* fmt, ...) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
 constexpr int kMaxDelay = 32;    // panel capacity of the delayed-update kernels

@@ -101,7 +101,11 @@ struct EngineW {
   static constexpr int LT = C::LT, RT = C::RT, NT = C::NT, JW = C::JW, RS = C::RS, TS = C::TS, GS = C::GS;
 
   WSmem<C>& sm;
-  const int tid, wave, lane, spin, wr, q, c;
+  // thread and wave indices; refresh_ids() re-derives them behind an opaque
+  // asm statement at the start of every window and measurement, so the
+  // compiler recomputes the addresses built from them there instead of
+  // hoisting dozens of them out of the loops into long-lived registers
+  int tid, wave, lane, spin, wr, q, c;
   double g[RT][NT][4];                                // this wave's tiles of G_spin
   uint64_t fm[JW];                                    // fields: bit set <=> s = -1 (uniform)
   int buf = 0;                                        // row-buffer parity (uniform)
@@ -119,6 +123,20 @@ struct EngineW {
         wr(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % C::WPS),
         q((threadIdx.x & 63) >> 4),
         c(threadIdx.x & 15) {}
+
+  __device__ __forceinline__ void refresh_ids() {
+    int t = threadIdx.x;
+    __asm__ volatile("" : "+v"(t));
+    tid = t;
+    lane = t & 63;
+    q = (t >> 4) & 3;
+    c = t & 15;
+    int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    __asm__ volatile("" : "+s"(w));
+    wave = w;
+    spin = w / C::WPS;
+    wr = w % C::WPS;
+  }
 
   template <class F>
   __device__ __forceinline__ void for_tiles(F&& f) {
@@ -161,24 +179,35 @@ struct EngineW {
   }
 
   // Rank-one update of both window blocks and of Q for an accepted slice j
-  // with factors f_s: u_s = f_s (B_s[:,j] - e_j), B_s += u_s B_s[j,:],
-  // Q_s += u_s Q_s[j,:].  Column j comes from lane 16q + j, row j from lane
-  // 16(j/4) + c, register j % 4.
+  // with factors f_s.  The wave keeps B'_s = B_s - 1 and Q'_s = Q_s - 1, so
+  // column j of B' is already B_s[:,j] - e_j: u_s = f_s B'_s[:,j],
+  // B'_s += u_s B_s[j,:], Q'_s += u_s Q_s[j,:] (rows of B and Q: the primed
+  // rows plus e_j).  Column j comes from lane 16q + j, row j from lane
+  // 16(j/4) + c, register j % 4 (a uniform choice: four branch leaves).
   __device__ __forceinline__ void rank1(int j, double fu, double fd, double (&bu)[4], double (&bd)[4],
                                         double (&qu)[4], double (&qd)[4]) {
     const int src_col = ((lane & 48) | j) << 2;
     const int src_row = (((j & 12) << 2) | c) << 2;
-    const int jr = j & 3;
+    double rbu = 0.0, rbd = 0.0, rqu = 0.0, rqd = 0.0;
+    dispatch<4>(j & 3, [&](auto jr) __attribute__((always_inline)) {
+      constexpr int R = decltype(jr)::value;
+      rbu = bperm_d(src_row, bu[R]);
+      rbd = bperm_d(src_row, bd[R]);
+      rqu = bperm_d(src_row, qu[R]);
+      rqd = bperm_d(src_row, qd[R]);
+    });
     double cu[4], cd[4];
     static_for<4>([&](auto r) __attribute__((always_inline)) {
       cu[r] = bperm_d(src_col, bu[r]);
       cd[r] = bperm_d(src_col, bd[r]);
     });
-    const double rbu = bperm_d(src_row, sel4(d4of(bu), jr)), rbd = bperm_d(src_row, sel4(d4of(bd), jr));
-    const double rqu = bperm_d(src_row, sel4(d4of(qu), jr)), rqd = bperm_d(src_row, sel4(d4of(qd), jr));
+    const double e = c == j ? 1.0 : 0.0;
+    rbu += e;
+    rbd += e;
+    rqu += e;
+    rqd += e;
     static_for<4>([&](auto r) __attribute__((always_inline)) {
-      const double e = (4 * q + r == j) ? 1.0 : 0.0;
-      const double au = fu * (cu[r] - e), ad = fd * (cd[r] - e);
+      const double au = fu * cu[r], ad = fd * cd[r];
       bu[r] = __builtin_fma(au, rbu, bu[r]);
       bd[r] = __builtin_fma(ad, rbd, bd[r]);
       qu[r] = __builtin_fma(au, rqu, qu[r]);
@@ -187,8 +216,9 @@ struct EngineW {
   }
 
   // Wave 0: the window's decisions.  Lane (q, c) with q == c/4 is the
-  // diagonal lane of window slice c (it holds G_s[c][c] in register c % 4).
-  // Writes P_s (window coordinates) and S to LDS.
+  // diagonal lane of window slice c (it holds B'_s[c][c] in register c % 4).
+  // Writes P_s (window coordinates) and S, |S| and the accepted slices in
+  // increasing order (4 bits each) to LDS.
   __device__ __forceinline__ void scan(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out,
                                        int b) {
     const int base = 16 * ww;
@@ -197,9 +227,10 @@ struct EngineW {
       const double* ru = sm.u.rows[b][0] + (4 * q) * RS + base + c;
       const double* rd = sm.u.rows[b][1] + (4 * q) * RS + base + c;
       static_for<4>([&](auto r) __attribute__((always_inline)) {
-        bu[r] = ru[r * RS];
-        bd[r] = rd[r * RS];
-        qu[r] = qd[r] = (4 * q + r == c) ? 1.0 : 0.0;
+        const double e = (4 * q + r == c) ? 1.0 : 0.0;
+        bu[r] = ru[r * RS] - e;
+        bd[r] = rd[r * RS] - e;
+        qu[r] = qd[r] = 0.0;
       });
     }
     const uint32_t fw0 = (uint32_t)(pick<JW>(fm, base >> 6) >> (base & 63)) & 0xFFFFu;
@@ -215,19 +246,21 @@ struct EngineW {
     double u = 0.0;
     if (mode == WM_METROPOLIS) u = bperm_d(((base + c) & 63) << 2, u01(pick<JW>(xw, ww >> 2)));
     uint32_t S = 0;
-    int l0 = 0;
+    uint64_t slist = 0, badmask = 0;
+    int m = 0, l0 = 0;
     for (;;) {
-      const double Ru = __builtin_fma(1.0 - sel4(d4of(bu), rr), du, 1.0);
-      const double Rd = __builtin_fma(1.0 - sel4(d4of(bd), rr), dd, 1.0);
+      // R_s = 1 + (1 - G_s[c][c]) d_s = 1 - B'_s[c][c] d_s
+      const double Ru = __builtin_fma(-sel4(d4of(bu), rr), du, 1.0);
+      const double Rd = __builtin_fma(-sel4(d4of(bd), rr), dd, 1.0);
       const double R = Ru * Rd;
       const bool live = dl && in && c >= l0 && (mode != WM_FORCE || c == jf);
       const uint64_t acc = __ballot(live && (mode != WM_METROPOLIS || u < R));
       const double Fu = du * recip(Ru), Fd = dd * recip(Rd);
       if (mode == WM_METROPOLIS) {
-        const uint64_t bad = __ballot(live && !(R > 0.0));
+        // R <= 0 (or not a number) among the slices this step rejects: every
+        // slice is rejected at most once, so the lanes can be collected
         const uint64_t below = acc ? ((1ull << __builtin_ctzll(acc)) - 1) : ~0ull;
-        nonpos += __builtin_popcountll(bad & below);
-        if (bad & below) err = 1;
+        badmask |= __ballot(live && !(R > 0.0)) & below;
       }
       if (!acc) break;
       const int lj = __builtin_ctzll(acc), j = lj & 15;
@@ -238,6 +271,8 @@ struct EngineW {
       }
       rank1(j, fu, fd, bu, bd, qu, qd);
       S |= 1u << j;
+      slist |= (uint64_t)j << (4 * m);
+      ++m;
       l0 = j + 1;
     }
     // P_s = D_s Q_s: row i scaled by the factor of slice i if accepted, else 0
@@ -248,13 +283,15 @@ struct EngineW {
       const int si = (fw0 >> i) & 1;
       const bool acc_i = (S >> i) & 1;
       const double fu_i = si ? fb : fa, fd_i = si ? fa : fb;
-      pu[r * TS] = acc_i ? fu_i * qu[r] : 0.0;
-      pd[r * TS] = acc_i ? fd_i * qd[r] : 0.0;
+      const double e = i == c ? 1.0 : 0.0;
+      pu[r * TS] = acc_i ? fu_i * (qu[r] + e) : 0.0;
+      pd[r * TS] = acc_i ? fd_i * (qd[r] + e) : 0.0;
     });
-    uint64_t slist = 0;
-    int m = 0;
-    for (uint32_t t = S; t; t &= t - 1, ++m) slist |= (uint64_t)__builtin_ctz(t) << (4 * m);
-    if (mode == WM_METROPOLIS) accepts += m;
+    if (mode == WM_METROPOLIS) {
+      accepts += m;
+      nonpos += __builtin_popcountll(badmask);
+      if (badmask) err = 1;
+    }
     if (lane == 0) {
       sm.win[0] = S;
       sm.win[1] = (uint32_t)m;
@@ -268,17 +305,25 @@ struct EngineW {
   // slices in order, columns = the tile's rows permuted so that the update's
   // fp64 accumulator lands in the tile layout), then for every tile column
   // G[r, tj] += V^T G[S, tj]: the accumulator registers of V are the A
-  // operands of the update, four accepted slices per instruction.
+  // operands of the update, four accepted slices per instruction.  K4 =
+  // ceil(|S| / 4) is a compile-time count in each of the four branches, so
+  // every operand load of a tile is issued before its matrix-core steps.
   template <bool FP32>
   __device__ __forceinline__ void flush(int ww, int m, uint64_t slist, int b) {
-    const int K4 = (m + 3) >> 2;
+    dispatch<4>((m - 1) >> 2, [&](auto kk) __attribute__((always_inline)) {
+      flush_k<FP32, decltype(kk)::value + 1>(ww, m, slist, b);
+    });
+  }
+
+  template <bool FP32, int K4>
+  __device__ __forceinline__ void flush_k(int ww, int m, uint64_t slist, int b) {
     const int ii = lane & 15, qq = lane >> 4;
     const double* pb = sm.pb[spin];
     const double* rows = sm.u.rows[b][spin];
     const int si = (int)(slist >> (4 * ii)) & 15;
-    int sk[4];
-    bool kv[4];
-    static_for<4>([&](auto gi) __attribute__((always_inline)) {
+    int sk[K4];
+    bool kv[K4];
+    static_for<K4>([&](auto gi) __attribute__((always_inline)) {
       const int k = 4 * gi + qq;
       kv[gi] = k < m;
       sk[gi] = (int)(slist >> (4 * k)) & 15;
@@ -288,38 +333,36 @@ struct EngineW {
     const int pi = FP32 ? ii : 4 * (ii & 3) + (ii >> 2);
     static_for<RT>([&](auto rt) __attribute__((always_inline)) {
       const int r = wr * RT + rt;
-      wd4 V = {0.0, 0.0, 0.0, 0.0};
       const double* tb = sm.tb[wave][rt];
-      static_for<4>([&](auto gi) __attribute__((always_inline)) {
-        if (gi < K4) {
-          const double a = (kv[gi] && ii < m) ? pb[sk[gi] * TS + si] : 0.0;
-          double bv = 0.0;
-          if (kv[gi]) {
-            bv = tb[pi * TS + sk[gi]];
-            if (r == ww && pi == sk[gi]) bv -= 1.0;
-          }
-          V = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, V, 0, 0, 0);
-        }
+      double av[K4], bv[K4];
+      static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+        const double x = pb[sk[gi] * TS + si];
+        const double y = tb[pi * TS + sk[gi]] - ((r == ww && pi == sk[gi]) ? 1.0 : 0.0);
+        av[gi] = (kv[gi] && ii < m) ? x : 0.0;
+        bv[gi] = kv[gi] ? y : 0.0;
+      });
+      wd4 V = {0.0, 0.0, 0.0, 0.0};
+      static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+        V = __builtin_amdgcn_mfma_f64_16x16x4f64(av[gi], bv[gi], V, 0, 0, 0);
       });
       static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        double rv[K4];
+        static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+          const double x = rows[sk[gi] * RS + 16 * tj + ii];
+          rv[gi] = kv[gi] ? x : 0.0;
+        });
         if constexpr (!FP32) {
           wd4 acc = {g[rt][tj][0], g[rt][tj][1], g[rt][tj][2], g[rt][tj][3]};
-          static_for<4>([&](auto gi) __attribute__((always_inline)) {
-            if (gi < K4) {
-              const double bv = kv[gi] ? rows[sk[gi] * RS + 16 * tj + ii] : 0.0;
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(V[decltype(gi)::value], bv, acc, 0, 0, 0);
-            }
+          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(V[decltype(gi)::value], rv[gi], acc, 0, 0, 0);
           });
           static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] = acc[decltype(r2)::value]; });
         } else {
           // fp32 products of four accepted slices each, added into the fp64 tile
-          static_for<4>([&](auto gi) __attribute__((always_inline)) {
-            if (gi < K4) {
-              const float bv = kv[gi] ? (float)rows[sk[gi] * RS + 16 * tj + ii] : 0.f;
-              wf4 p = {0.f, 0.f, 0.f, 0.f};
-              p = __builtin_amdgcn_mfma_f32_16x16x4f32((float)V[decltype(gi)::value], bv, p, 0, 0, 0);
-              static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] += (double)p[decltype(r2)::value]; });
-            }
+          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+            wf4 p = {0.f, 0.f, 0.f, 0.f};
+            p = __builtin_amdgcn_mfma_f32_16x16x4f32((float)V[decltype(gi)::value], (float)rv[gi], p, 0, 0, 0);
+            static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] += (double)p[decltype(r2)::value]; });
           });
         }
       });
@@ -328,6 +371,7 @@ struct EngineW {
 
   // One window on every wave.  Returns the accepted slice mask.
   __device__ __forceinline__ uint32_t window(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out) {
+    refresh_ids();
     const int b = buf;
     buf ^= 1;
     publish_rows(ww, b);
@@ -355,26 +399,21 @@ struct EngineW {
   }
 
   // ---------------------------------------------------------------- measurement
-  // Sum over rows i in [r0, r0 + nr) of eps G[i][(i - k) mod L] for the
-  // dumped rows (row i at (i - r0) * GS): the part of S_k = sum_l eps
-  // G[(l + k) mod L][l] (eps = -1 where l + k wraps) held by the block.
-  __device__ __forceinline__ double diag_block(const double* m, int k, int r0, int nr) const {
-    double a0 = 0.0, a1 = 0.0;
-    const int r1 = r0 + nr < L ? r0 + nr : L;
-    int i = r0;
-    // rows i < k wrap (l = i - k + L, eps = -1), rows i >= k do not
-    const int split = k < r0 ? r0 : (k < r1 ? k : r1);
-    for (; i + 2 <= split; i += 2) {
-      a0 -= m[(i - r0) * GS + i - k + L];
-      a1 -= m[(i + 1 - r0) * GS + i + 1 - k + L];
+  // Part of S_k = sum_l eps G[(l + k) mod L][l] (eps = -1 where l + k
+  // wraps, i.e. for rows i < k) held by dumped rows i in [i0, i0 + n) ∩
+  // [0, L) (row i at (i - r0) * GS).  Eight independent partial sums with
+  // compile-time indices, so eight loads are in flight at a time.
+  __device__ __forceinline__ double diag_part(const double* m, int k, int r0, int i0, int n) const {
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < n; t0 += 8) {
+      static_for<8>([&](auto u) __attribute__((always_inline)) {
+        const int i = i0 + t0 + u;
+        const bool wrap = i < k;
+        const double x = m[(i - r0) * GS + (wrap ? i - k + L : i - k)];
+        a[u] += (t0 + u < n && i < L) ? (wrap ? -x : x) : 0.0;
+      });
     }
-    for (; i < split; ++i) a0 -= m[(i - r0) * GS + i - k + L];
-    for (; i + 2 <= r1; i += 2) {
-      a0 += m[(i - r0) * GS + i - k];
-      a1 += m[(i + 1 - r0) * GS + i + 1 - k];
-    }
-    for (; i < r1; ++i) a0 += m[(i - r0) * GS + i - k];
-    return a0 + a1;
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
 
   // Write rows [r0, r0 + DR) of this wave's tiles into the dump.
@@ -390,16 +429,27 @@ struct EngineW {
     });
   }
 
-  // S_k of G_up and G_dn for thread k < L (other threads get 0).  The rows
-  // buffers are reused for the dump, one spin and DR rows at a time.
+  // Partial S_k of G_up and G_dn: thread t < NP * L takes k = t % L and the
+  // part t / L of every dumped block of rows (NP parts of DR / NP rows);
+  // other threads get 0.  The rows buffers are reused for the dump, one spin
+  // and DR rows at a time.
+  static constexpr int NP = (C::NTH / LT) >= 4 ? 4 : ((C::NTH / LT) >= 2 ? 2 : 1);
   __device__ __forceinline__ void green_sums(double& su_k, double& sd_k) {
     su_k = sd_k = 0.0;
+    const int k = tid % L, part = tid / L;
+    constexpr int RP = C::DR / NP;  // rows of a block per part
     static_for<2>([&](auto s) __attribute__((always_inline)) {
       for (int r0 = 0; r0 < L; r0 += C::DR) {
         __syncthreads();
         if (spin == s) dump_rows(r0);
         __syncthreads();
-        if (tid < L) (s == 0 ? su_k : sd_k) += diag_block(sm.u.dump, tid, r0, C::DR);
+        if (part < NP) {
+          const double x = diag_part(sm.u.dump, k, r0, r0 + part * RP, RP);
+          if (s == 0)
+            su_k += x;
+          else
+            sd_k += x;
+        }
       }
     });
     __syncthreads();
@@ -455,6 +505,11 @@ struct EngineW {
 
   __device__ __forceinline__ double* state_ptr(uint8_t* ws) const {
     return reinterpret_cast<double*>(ws + d.off_state) + (size_t)tid * (RT * NT * 4);
+  }
+  // parked parts of the g(tau) bin sums: 2 NP L doubles in the second
+  // 2 LT^2 region of the state area (which these kernels do not otherwise use)
+  __device__ __forceinline__ double* gpart_state(uint8_t* ws) const {
+    return reinterpret_cast<double*>(ws + d.off_state) + 2 * (size_t)LT * LT;
   }
   __device__ __forceinline__ double* lsum_state(uint8_t* ws) const {
     return reinterpret_cast<double*>(ws + d.off_state) + 4 * (size_t)LT * LT;
@@ -514,11 +569,16 @@ struct EngineW {
     const bool sweeps = d.op == OP_SWEEPS;
     const int64_t nm = d.n_measure, nb = d.n_bins;
     double su = 0.0, sd = 0.0, sx = 0.0;  // wave 0: per-lane sums of 1-G_up, 1-G_dn and their product
-    double gau = 0.0, gad = 0.0;          // thread k < L: running bin sums of g_up(tau_k), g_dn(tau_k)
+    // thread t < NP L: its part of the running bin sums of g_up(tau_k),
+    // g_dn(tau_k), k = t % L; the parts are added in a fixed order when the
+    // bin completes, and parked part by part when a launch ends inside a bin,
+    // so a chain split over launches sums in exactly the order of one launch
+    double gau = 0.0, gad = 0.0;
     int64_t cur_bin = -1;
+    bool cont = false;  // this launch starts inside a bin a previous one left open
     if (sweeps) {
       const int64_t m0 = d.sweep_begin - d.n_warmup;
-      const bool cont = (flags & F_RESUME) && m0 > 0 && m0 < nm && (m0 * nb) / nm == ((m0 - 1) * nb) / nm;
+      cont = (flags & F_RESUME) && m0 > 0 && m0 < nm && (m0 * nb) / nm == ((m0 - 1) * nb) / nm;
       if (cont && wave == 0) {
         const double* la = lsum_state(ws);
         su = la[lane];
@@ -596,22 +656,27 @@ struct EngineW {
       }
       if (!measure || w - 1 < d.n_warmup) continue;
       // ---- measurement of sweep w - 1
+      refresh_ids();
       const int64_t m = w - 1 - d.n_warmup;
       const int64_t b = (m * nb) / nm;
       double* bp = bins + (size_t)b * NV;
       if (b != cur_bin) {
-        gau = tid < L ? bp[tid] : 0.0;
-        gad = tid < L ? bp[L + 1 + tid] : 0.0;
+        gau = gad = 0.0;
+        if (cont && tid < NP * L) {
+          const double* pk = gpart_state(ws);
+          gau = pk[tid];
+          gad = pk[NP * L + tid];
+        }
+        cont = false;
         cur_bin = b;
       }
+      write_diag();  // read by wave 0 after the barriers of the g(tau) sums
       {
         double xu, xd;
         green_sums(xu, xd);
         gau += xu / (double)L;
         gad += xd / (double)L;
       }
-      write_diag();
-      __syncthreads();
       if (wave == 0) {
         static_for<JW>([&](auto jj) __attribute__((always_inline)) {
           const int mm = lane + 64 * jj;
@@ -624,10 +689,23 @@ struct EngineW {
         });
       }
       if ((m + 1 == nm) || (((m + 1) * nb) / nm != b)) {  // the bin is complete
-        if (tid < L) {
-          bp[tid] = gau;
-          bp[L + 1 + tid] = gad;
+        // parts 1.. hand their sums to part 0 through the (free) dump area
+        const int part = tid / L;
+        if (part >= 1 && part < NP) {
+          sm.u.dump[(part - 1) * 2 * L + tid % L] = gau;
+          sm.u.dump[(part - 1) * 2 * L + L + tid % L] = gad;
         }
+        __syncthreads();
+        if (tid < L) {
+          double xu = gau, xd = gad;
+          for (int pp = 1; pp < NP; ++pp) {
+            xu += sm.u.dump[(pp - 1) * 2 * L + tid];
+            xd += sm.u.dump[(pp - 1) * 2 * L + L + tid];
+          }
+          bp[tid] = xu;
+          bp[L + 1 + tid] = xd;
+        }
+        __syncthreads();
         cur_bin = -1;
         if (wave == 0) {
           const double nu = wave_sum(su) / (double)L, nd = wave_sum(sd) / (double)L;
@@ -647,10 +725,10 @@ struct EngineW {
       // a bin still open when this launch ends: park its running sums
       const int64_t ml = d.sweep_end - 1 - d.n_warmup;
       if (d.sweep_end > d.sweep_begin && ml >= 0 && ml + 1 < nm && ((ml + 1) * nb) / nm == (ml * nb) / nm) {
-        double* bp = bins + (size_t)((ml * nb) / nm) * NV;
-        if (tid < L) {
-          bp[tid] = gau;
-          bp[L + 1 + tid] = gad;
+        if (tid < NP * L) {
+          double* pk = gpart_state(ws);
+          pk[tid] = gau;
+          pk[NP * L + tid] = gad;
         }
         if (wave == 0) {
           double* la = lsum_state(ws);
