@@ -149,6 +149,22 @@ hfqmc_status hfqmc_workspace_size(hfqmc_ctx *ctx, const hfqmc_problem *problems,
 hfqmc_status hfqmc_solve(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
                          hfqmc_result *out);
 
+/* Bytes of the library's own device array used by hfqmc_solve_static. */
+#define HFQMC_STATIC_BYTES ((size_t)64 << 20)
+
+/* hfqmc_solve on the library's own device array of HFQMC_STATIC_BYTES per
+ * device instead of a caller workspace.  For callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc): it allocates nothing, and the context's streams and
+ * events already exist from hfqmc_create.  HFQMC_EINVAL, with nothing run,
+ * if hfqmc_workspace_size of the batch exceeds HFQMC_STATIC_BYTES (at L = 64
+ * about 390 impurities fit).  Every call on a device uses the same array, so
+ * calls that overlap on one device (from several contexts or threads) race;
+ * a call leaves the array holding its batch, and the next call restages
+ * every input and clears every accumulator it reads.  Results as
+ * hfqmc_solve. */
+hfqmc_status hfqmc_solve_static(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, hfqmc_result *out);
+
 /* Split form of hfqmc_solve.  stage: validate, plan, copy inputs to d_ws
  * (blocking).  run: enqueue the whole device pass (field initialisation,
  * Dyson, sweeps, measurement) on the context stream, asynchronous; may be

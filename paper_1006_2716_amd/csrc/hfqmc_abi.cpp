@@ -79,6 +79,34 @@ hfqmc_status fail(hfqmc_status s, const char* fmt, ...) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// The device array behind hfqmc_solve_static, and its address on each device
+// (resolved once per device by hfqmc_create with that device current: in
+// host code the array's name is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[HFQMC_STATIC_BYTES];
+
+namespace {
+
+hfqmc_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(HFQMC_EINVAL, "device %d outside [0,%d)", device, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HFQMC_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return fail(HFQMC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch_ptr[device] = p;
+  return HFQMC_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
@@ -1215,6 +1243,17 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     return fail(HFQMC_EDEVICE, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
   }
   c->n_cu = prop.multiProcessorCount;
+  // set-up for hfqmc_solve_static, with the device current: the static
+  // array's device address, and the streams and events every pass uses, so
+  // that call creates and allocates nothing
+  if (hfqmc_status st = scratch_setup(device)) {
+    delete c;
+    return st;
+  }
+  if (hfqmc_status st = ensure_streams(c)) {
+    delete c;
+    return st;
+  }
   if (tune_cache) {
     c->tune_path = tune_cache;
     c->tune_all = read_tune_cache(c->tune_path);
@@ -1280,6 +1319,29 @@ hfqmc_status hfqmc_run(hfqmc_ctx* c) {
   c->last_launches = (int)c->groups.size();
   c->last_timed_groups = true;
   return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_solve_static(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, hfqmc_result* out) {
+  if (!c || !p || n < 1 || !out) return fail(HFQMC_EINVAL, "hfqmc_solve_static: bad arguments");
+  size_t need = 0;
+  TRY(hfqmc_workspace_size(c, p, n, &need));
+  if (need > HFQMC_STATIC_BYTES)
+    return fail(HFQMC_EINVAL, "hfqmc_solve_static: the batch needs %zu bytes of workspace, the static array holds %zu",
+                need, (size_t)HFQMC_STATIC_BYTES);
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return fail(HFQMC_EDEVICE, "hfqmc_solve_static: no static array on device %d", c->device);
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    TRY(stage_impl(c, p, n, ws, HFQMC_STATIC_BYTES, nullptr));
+    TRY(set_device(c));
+    // the whole pass, timed only by the start/end events created with the context
+    HIP_TRY(hipEventRecord(c->ev_start, c->stream));
+    TRY(enqueue_pass(c, c->stream, false));
+    HIP_TRY(hipEventRecord(c->ev_end, c->stream));
+    c->last_launches = (int)c->groups.size();
+    c->last_timed_groups = false;
+  }
+  return hfqmc_collect(c, out);
 }
 
 hfqmc_status hfqmc_run_graph(hfqmc_ctx* c) {

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libhfqmc.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENUMERIC, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
+STATIC_BYTES = 64 << 20  # HFQMC_STATIC_BYTES: the device array of hfqmc_solve_static
 
 
 class HFQMCError(RuntimeError):
@@ -74,6 +75,7 @@ def lib():
             "hfqmc_create": [C.c_int, _VP, C.c_int, C.c_char_p, C.POINTER(_VP)],
             "hfqmc_workspace_size": [_VP, C.POINTER(Problem), C.c_int32, C.POINTER(C.c_size_t)],
             "hfqmc_solve": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t, C.POINTER(Result)],
+            "hfqmc_solve_static": [_VP, C.POINTER(Problem), C.c_int32, C.POINTER(Result)],
             "hfqmc_stage": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t],
             "hfqmc_run": [_VP],
             "hfqmc_collect": [_VP, C.POINTER(Result)],
@@ -308,6 +310,19 @@ class Context:
         self.stage(problems, workspace)
         self.run()
         return self.collect()
+
+    def solve_static(self, problems):
+        """hfqmc_solve_static: the batch on the library's own device array
+        (no workspace, nothing allocated); raises HFQMCError(EINVAL) when the
+        batch needs more than STATIC_BYTES."""
+        P = _Problems(problems)
+        R = _Results(problems)
+        st = lib().hfqmc_solve_static(self.h, P.arr, P.n, R.arr)
+        res = R.to_list()
+        if st not in (OK, ENUMERIC):
+            _check(st, "hfqmc_solve_static")
+        self._staged = None
+        return res
 
     def stage(self, problems, workspace=None):
         if workspace is None:
