@@ -124,6 +124,8 @@ typedef struct {
     int64_t accepts;
     int64_t nonpositive;        /* proposals rejected because R <= 0 */
     int32_t status;             /* hfqmc_status of this impurity */
+    int32_t recoveries;         /* sweeps repeated after a ratio that was not a
+                                   positive number (see numeric recovery below) */
 } hfqmc_result;
 
 /* lambda from cosh(lambda) = exp(dtau U / 2) (paper: HF discretisation of
@@ -148,6 +150,31 @@ hfqmc_status hfqmc_workspace_size(hfqmc_ctx *ctx, const hfqmc_problem *problems,
  * out: n caller-owned results.  Equivalent to stage + run + collect. */
 hfqmc_status hfqmc_solve(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
                          hfqmc_result *out);
+
+/* ---- numeric recovery and drift control ----
+ * Every Metropolis sweep checks its ratios R = R_up R_dn (Eq. (1)); in exact
+ * arithmetic they are positive.  A sweep that meets one that is not a
+ * positive number (R <= 0, NaN, a non-finite G) is undone -- fields,
+ * counters -- and repeated once from a from-scratch fp64 Dyson solve
+ * (Eq. (2)) of its starting fields; the result's `recoveries` counts these.
+ * If the repeat fails too, the impurity's status is HFQMC_ENUMERIC.  A
+ * recovered sweep takes the decisions of an undisturbed one, so results
+ * agree with a run that never failed up to rounding.
+ *
+ * Drift limit (per context; HFQMC_FP64 default 0 = off, HFQMC_MIXED default
+ * 1e-6): a scheduled from-scratch recompute that finds max |G_updated -
+ * G_recomputed| over the diagonal 16 x 16 blocks above the limit halves the
+ * interval to the next recompute (kept across the launches of a chain); if
+ * the interval is already 1 sweep, the impurity ends HFQMC_ENUMERIC.  EINVAL
+ * unless 0 <= limit < inf.  Applies to problems staged afterwards. */
+hfqmc_status hfqmc_set_drift_limit(hfqmc_ctx *ctx, double limit);
+
+/* Test hook for the numeric recovery: the Metropolis ratios of sweep
+ * `sweep_a` (first attempt) and of the repeated attempt of sweep `sweep_b`
+ * are formed from a NaN-poisoned copy of G's diagonal (blocks), as a
+ * non-finite G would give; -1 disables either.  Global sweep indices
+ * (warm-up included) of every chain of problems staged afterwards. */
+hfqmc_status hfqmc_debug_poison(hfqmc_ctx *ctx, int64_t sweep_a, int64_t sweep_b);
 
 /* Bytes of the library's own device array used by hfqmc_solve_static. */
 #define HFQMC_STATIC_BYTES ((size_t)64 << 20)

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhfqmc.so")
 SOURCES = ["hfqmc_sweep.hip", "hfqmc_sweep_global.hip", "hfqmc_window.hip", "hfqmc_window_mixed.hip",
+           "hfqmc_window_global.hip",
            "hfqmc_lattice.hip", "hfqmc_abi.cpp"]
 
 HIPCC_FLAGS = [

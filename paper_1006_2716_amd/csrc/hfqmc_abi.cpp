@@ -111,6 +111,9 @@ void* scratch_ptr(int device) {
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
 constexpr int kMaxDelay = 32;    // panel capacity of the delayed-update kernels
+// Default drift limit of HFQMC_MIXED contexts: fp32 products in the window
+// flush; far below the statistical errors of the estimators (1e-3 .. 1e-2).
+constexpr double kMixedDriftLimit = 1e-6;
 constexpr int kAuxStreams = 3;   // extra streams for concurrent kernel classes
 constexpr int kSrvStreams = 6;   // serving launch streams
 constexpr int kMaxChains = 64;   // independent chains per problem
@@ -140,8 +143,10 @@ int kernel_LT(int L, int dk) { return is_window(dk) && L <= kMaxRegisterL ? wind
 // Padded slice counts at which the untuned default is the window kernel
 // (elsewhere the rank-one kernel, measured faster there on MI355X).
 bool window_default(int LT) {
-  (void)LT;
-  return false;
+  // 512 impurities of the chain workload: 158 against 228 ms at 80 slices,
+  // 245 against 284 ms at 96; at 32-64 slices the rank-one kernels are
+  // 8-16 % faster, at 128 the two take the same time
+  return LT == 80 || LT == 96;
 }
 
 // Untuned tile-rows per wave of the window kernels: the flush is spread over
@@ -257,6 +262,7 @@ void pool_chain(int NV, int nb, const double* sums, const ImpStatus& st, double*
   pst.nonpositive += st.nonpositive;
   pst.error |= st.error;
   pst.max_drift = std::max(pst.max_drift, st.max_drift);
+  pst.recoveries += st.recoveries;
 }
 
 // Bin means and errors from per-bin sums and measurement counts (pooled over
@@ -295,6 +301,7 @@ void finalise(int L, int nb, const double* sums, const int64_t* cnt, const ImpSt
   r.nonpositive = st.nonpositive;
   r.accept_rate = st.proposals ? (double)st.accepts / (double)st.proposals : 0.0;
   r.max_drift = st.max_drift;
+  r.recoveries = st.recoveries;
   bool finite = std::isfinite(r.n[0]) && std::isfinite(r.n[1]) && std::isfinite(r.docc);
   r.status = (st.error || !finite) ? HFQMC_ENUMERIC : HFQMC_OK;
 }
@@ -624,9 +631,19 @@ struct hfqmc_ctx {
   std::vector<PoolBlock> free_list;
   std::vector<hfqmc_site*> sites;
   Server srv;
+  // per-chain settings copied into every descriptor
+  double drift_limit = 0.0;
+  int64_t poison[2] = {0, 0};  // test hook: 1 + sweep, 0 = none
 };
 
 namespace {
+
+// The context's per-chain settings into a descriptor (after fill_constants).
+void apply_settings(ImpDesc& d, const hfqmc_ctx* c) {
+  d.drift_limit = c->drift_limit;
+  d.poison[0] = c->poison[0];
+  d.poison[1] = c->poison[1];
+}
 
 hfqmc_status set_device(hfqmc_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
@@ -696,16 +713,27 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
   if (p.delay == 0 && tuned) {
     pl.k = it->second.k;
     pl.rt = it->second.rt;
-    pl.dk = pl.k == 0 ? dk_window : (pl.rt == 0 ? 1 : (pl.k > 1 ? dk_delayed : 0));
+    if (pl.k == 0)  // window updates; fp64 where no fp32-product variant exists
+      pl.dk = LT <= kMaxRegisterL && find_kernel(window_LT(p.L), pl.rt, dk_window) ? dk_window : kDkWindow;
+    else
+      pl.dk = pl.rt == 0 ? 1 : (pl.k > 1 ? dk_delayed : 0);
   } else if (LT > kMaxRegisterL) {
-    // only the global-memory kernel (fp64 delayed updates) handles these
+    // G in device memory: fp64 window updates (delay 0), or fp64 delayed
+    // updates of the given depth
     pl.rt = 0;
-    pl.dk = 1;
-    pl.k = p.delay >= 1 ? p.delay : kGlobalMaxDelay;
-  } else if (p.delay == 0 && window_default(window_LT(p.L))) {
-    pl.dk = dk_window;
+    if (p.delay == 0 && find_kernel(LT, 0, kDkWindow)) {
+      pl.dk = kDkWindow;
+      pl.k = 0;
+    } else {
+      pl.dk = 1;
+      pl.k = p.delay >= 1 ? p.delay : kGlobalMaxDelay;
+    }
+  } else if (p.delay == 0 && (c->prec == HFQMC_MIXED || window_default(window_LT(p.L)))) {
+    // mixed precision: the window kernel with fp32 flush products where one
+    // is compiled for the class, else the fp64 one
     pl.k = 0;
     pl.rt = default_rt_window(window_LT(p.L));
+    pl.dk = find_kernel(window_LT(p.L), pl.rt, dk_window) ? dk_window : kDkWindow;
   } else if (p.delay <= 1) {
     pl.rt = tuned && it->second.k == 1 ? it->second.rt : default_rt(LT, 0);
   } else {
@@ -785,6 +813,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
   for (int i = 0; i < n; ++i) {
     ImpDesc d{};
     fill_constants(d, p[i]);
+    apply_settings(d, c);
     d.LT = plan[i].LT;
     d.op = OP_SWEEPS;
     d.delay = plan[i].k;
@@ -1101,6 +1130,7 @@ bool srv_step(hfqmc_ctx* c) {
         if (r->q[j] == 0) continue;
         ImpDesc d{};
         fill_constants(d, r->prob);
+        apply_settings(d, c);
         site_offsets(r->site, d, j);
         d.op = OP_SWEEPS;
         d.n_measure = chain_measure(r->prob, j);
@@ -1231,6 +1261,7 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->prec = precision;
+  c->drift_limit = precision == HFQMC_MIXED ? kMixedDriftLimit : 0.0;
   hipDeviceProp_t prop;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
@@ -1261,7 +1292,9 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
       if (t.prec != prec_name(precision)) continue;
       if (t.k == 0) {  // window updates
         const int dk = precision == HFQMC_MIXED ? kDkWindowMixed : kDkWindow;
-        if (t.LT <= kMaxRegisterL && find_kernel(window_LT(t.LT), t.rt, dk)) c->tune[t.LT] = t;
+        if (t.LT <= kMaxRegisterL ? find_kernel(window_LT(t.LT), t.rt, dk) != nullptr
+                                  : (t.rt == 0 && find_kernel(t.LT, 0, kDkWindow) != nullptr))
+          c->tune[t.LT] = t;
         continue;
       }
       const int dk = t.rt == 0 ? 1 : (t.k > 1 ? (precision == HFQMC_MIXED ? 2 : 1) : 0);
@@ -1318,6 +1351,21 @@ hfqmc_status hfqmc_run(hfqmc_ctx* c) {
   HIP_TRY(hipEventRecord(c->ev_end, c->stream));
   c->last_launches = (int)c->groups.size();
   c->last_timed_groups = true;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_set_drift_limit(hfqmc_ctx* c, double limit) {
+  if (!c || !(limit >= 0.0) || !std::isfinite(limit)) return fail(HFQMC_EINVAL, "hfqmc_set_drift_limit: need limit >= 0");
+  std::lock_guard<std::mutex> g(c->mu);
+  c->drift_limit = limit;
+  return HFQMC_OK;
+}
+
+hfqmc_status hfqmc_debug_poison(hfqmc_ctx* c, int64_t sweep_a, int64_t sweep_b) {
+  if (!c || sweep_a < -1 || sweep_b < -1) return fail(HFQMC_EINVAL, "hfqmc_debug_poison: sweeps must be >= -1");
+  std::lock_guard<std::mutex> g(c->mu);
+  c->poison[0] = sweep_a + 1;
+  c->poison[1] = sweep_b + 1;
   return HFQMC_OK;
 }
 
@@ -1472,6 +1520,8 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
     for (int v = 0; v < nv; ++v)
       for (int k : {4, 8, 16, 32})
         if (rts[v] != 0) cands.push_back({rts[v], dk_delayed, k});
+    if (find_kernel(LT, 0, kDkWindow))  // device-memory window updates (fp64 in either precision)
+      cands.push_back({0, kDkWindow, 0});
     if (find_kernel(LT, 0, 1))  // the global-memory kernel (fp64 flushes in either precision)
       for (int k : {4, 8, 16}) cands.push_back({0, 1, k});
     TuneEntry best{prec_name(c->prec), LT, 0, 0, -1.0, ""};
@@ -1628,6 +1678,7 @@ hfqmc_status hfqmc_site_set_fields(hfqmc_ctx* c, hfqmc_site* s, const int8_t* fi
   HIP_TRY(hipMemcpyAsync(c->pool + s->off + s->o_init, fields, s->L, hipMemcpyHostToDevice, c->stream));
   ImpDesc d{};
   fill_constants(d, s->prob);
+  apply_settings(d, c);
   d.op = OP_FORCE;
   d.n_force = 0;
   d.flags = F_FIELDS_GIVEN | F_SAVE | F_ZERO_ACC;
@@ -1651,6 +1702,8 @@ hfqmc_status hfqmc_site_force_flips(hfqmc_ctx* c, hfqmc_site* s, const int32_t* 
     HIP_TRY(hipMemcpyAsync(base + s->o_force, slices + k0, sizeof(int32_t) * m, hipMemcpyHostToDevice, c->stream));
     ImpDesc d{};
     fill_constants(d, s->prob);
+    apply_settings(d, c);
+  apply_settings(d, c);
     d.op = OP_FORCE;
     d.n_force = m;
     d.flags = F_RESUME | F_SAVE;
@@ -1672,6 +1725,7 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx* c, hfqmc_site* s, double* drift) {
   TRY(set_device(c));
   ImpDesc d{};
   fill_constants(d, s->prob);
+  apply_settings(d, c);
   d.op = OP_RECOMPUTE;
   d.flags = F_RESUME | F_SAVE | F_ZERO_ACC;
   TRY(site_launch(c, s, d));

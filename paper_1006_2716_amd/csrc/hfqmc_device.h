@@ -116,6 +116,14 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Marks slice l in a uniform bit mask of JW words (slice m: word m / 64).
+template <int JW>
+__device__ __forceinline__ void mark_flip(uint64_t (&fl)[JW], int l) {
+  static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+    if (jj == (l >> 6)) fl[jj] ^= 1ull << (l & 63);
+  });
+}
+
 // Per-wave copy of an impurity's slice state: slice m lives in lane m % 64,
 // word m / 64.  Every wave of the workgroup keeps its own copy and takes the
 // same Metropolis decisions from it, so rejections need no communication.
@@ -194,5 +202,6 @@ struct KernelInfo {
 // Kernels of the other translation units.
 int global_kernels(const KernelInfo** list);
 int window_kernels(const KernelInfo** list);
+int window_global_kernels(const KernelInfo** list);
 
 }  // namespace hfqmc

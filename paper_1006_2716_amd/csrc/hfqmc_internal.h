@@ -62,15 +62,25 @@ struct alignas(16) ImpDesc {
   int64_t off_force;        // OP_FORCE: n_force int32 slices, then n_force doubles ratios
   int64_t off_init;         // F_FIELDS_GIVEN: L int8 initial fields (read only)
   int64_t chain;            // chain index of this impurity: Philox counter word 3
+  double drift_limit;       // > 0: a scheduled recompute that measures more drift halves
+                            // the interval to the next one; at interval 1 it is an error
+  int64_t poison[2];        // test hook, 0 = none: the ratios of the first attempt of sweep
+                            // poison[0] - 1 and of the repeated attempt of sweep
+                            // poison[1] - 1 read a NaN-poisoned diagonal of G
 };
 
 struct alignas(16) ImpStatus {
   int64_t proposals;
   int64_t accepts;
   int64_t nonpositive;
-  int64_t error;            // nonzero: non-finite ratio or Green function seen
+  int64_t error;            // nonzero: non-finite ratio or Green function seen and not
+                            // recovered, or the drift limit exceeded at one sweep
   double max_drift;         // max |G_updated - G_recomputed| over recomputes
-  double pad[3];
+  int64_t next_rec;         // drift limit on: sweep of the next from-scratch Dyson solve
+  int32_t rec_every;        // drift limit on: current sweeps between Dyson solves (0: unset)
+  int32_t recoveries;       // sweeps repeated after a ratio that was not a positive number,
+                            // each from a from-scratch Dyson solve of its starting fields
+  double pad;
 };
 
 // Number of measured values per bin: g_up(0..L), g_dn(0..L), n_up, n_dn, d.

@@ -286,17 +286,19 @@ struct Engine : SliceState<C::JW> {
             }
             static_for<4>([&](auto r) __attribute__((always_inline)) { gset(rt, tj, r, acc[decltype(r)::value]); });
           } else {
+            // fp32 products of four updates at a time, each group added into
+            // the fp64 tile (no fp32 sum across groups)
             typedef float f4 __attribute__((ext_vector_type(4)));
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
             for (int k0 = 0; k0 < kb; k0 += 4) {
               const int k = k0 + kk;
               const float av = k < kb ? (float)W.pa[spin][k][ti * 16 + arow] : 0.f;
               const float bv = k < kb ? (float)W.pb[spin][k][tj * 16 + ii] : 0.f;
+              f4 acc = {0.f, 0.f, 0.f, 0.f};
               acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+              static_for<4>([&](auto r) __attribute__((always_inline)) {
+                gset(rt, tj, r, gget(rt, tj, r) + (double)acc[decltype(r)::value]);
+              });
             }
-            static_for<4>([&](auto r) __attribute__((always_inline)) {
-              gset(rt, tj, r, gget(rt, tj, r) + (double)acc[decltype(r)::value]);
-            });
           }
         });
       });
@@ -354,6 +356,15 @@ struct Engine : SliceState<C::JW> {
     });
   }
 
+  // Test hook: the diagonal copies the ratios read times x (1 leaves them
+  // unchanged, NaN poisons them).
+  __device__ __forceinline__ void scale_diag(double x) {
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      dgu[jj] *= x;
+      dgd[jj] *= x;
+    });
+  }
+
   __device__ __forceinline__ void load_tiles(uint8_t* ws) {
     const double* p = state_ptr(ws);
     for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
@@ -363,9 +374,18 @@ struct Engine : SliceState<C::JW> {
 
   // Dyson equation from scratch: G = G0, then switch every slice's potential
   // from 0 to s*lambda*s_l by a rank-one update.  Returns max |G_old - G_new|
-  // (uniform) when `drift` is set; G_old is parked in the state area.
+  // over the diagonal 16 x 16 tiles (uniform) when `drift` is set; the old
+  // diagonal tiles are kept in registers meanwhile.
   __device__ __forceinline__ double recompute(uint8_t* ws, bool drift) {
-    if (drift) save_tiles(ws);
+    double dt[RT][4] = {};
+    if (drift) {
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+          if (tj == wr * RT + rt)
+            static_for<4>([&](auto r) __attribute__((always_inline)) { dt[rt][r] = gget(rt, tj, r); });
+        });
+      });
+    }
     // G = G0, the antiperiodic matrix of this wave's spin, element by element
     // from the Weiss samples in LDS
     for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
@@ -393,9 +413,13 @@ struct Engine : SliceState<C::JW> {
     }
     double dr = 0.0;
     if (drift) {
-      const double* p = state_ptr(ws);
-      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
-        dr = fmax(dr, fabs(p[(rt * NT + tj) * 4 + r] - gget(rt, tj, r)));
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+          if (tj == wr * RT + rt)
+            static_for<4>([&](auto r) __attribute__((always_inline)) {
+              dr = fmax(dr, fabs(dt[rt][r] - gget(rt, tj, r)));
+            });
+        });
       });
       dr = wave_max(dr);
       if (lane == 0) sm.red[wave] = dr;
@@ -478,7 +502,16 @@ struct Engine : SliceState<C::JW> {
       if (tid == 0) {
         st->proposals = st->accepts = st->nonpositive = st->error = 0;
         st->max_drift = 0.0;
+        st->recoveries = 0;
       }
+    }
+    // recompute schedule: every recompute_every sweeps, or with a drift limit
+    // the (possibly shortened) schedule a previous launch of the chain left
+    int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+    int rec_every = d.recompute_every;
+    if (d.drift_limit > 0.0 && !(flags & F_ZERO_ACC) && st->rec_every > 0) {
+      next_rec = st->next_rec;
+      rec_every = st->rec_every;
     }
     for (int i = tid; i < 2 * LT; i += C::NTH) {
       const int s = i / LT, k = i % LT;
@@ -506,6 +539,7 @@ struct Engine : SliceState<C::JW> {
     int64_t proposals = 0, accepts = 0, nonpos = 0;
     int64_t err = 0;
     double max_drift = 0.0;
+    int recoveries = 0;
 
     if (d.op == OP_SWEEPS) {
       // Running bin sums.  They are loaded when a bin is entered and stored
@@ -539,8 +573,15 @@ struct Engine : SliceState<C::JW> {
           });
         }
       }
-      int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+      // numeric recovery: a sweep whose scan saw a ratio that was not a
+      // positive number is repeated once, from its starting fields and a
+      // from-scratch Dyson solve; the repeat failing too leaves the error set
+      int attempt = 0;
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
+        uint64_t fl[JW];  // slices flipped in this sweep (uniform)
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) { fl[jj] = 0; });
+        const int64_t pr0 = proposals, acc0 = accepts, np0 = nonpos, err0 = err;
+        scale_diag((attempt ? +d.poison[1] : +d.poison[0]) == w + 1 ? __builtin_nan("") : 1.0);
         double uv[JW];
         {
           const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
@@ -560,6 +601,7 @@ struct Engine : SliceState<C::JW> {
             __syncthreads();
             fetch(l, fu, fd, a, b);
             flip_field(l);
+            mark_flip(fl, l);
             proposals += l - l0 + 1;
             ++accepts;
             l0 = l + 1;
@@ -571,6 +613,7 @@ struct Engine : SliceState<C::JW> {
             delayed_append(l, fu, fd);
             if (kb >= kdepth) flush();
             flip_field(l);
+            mark_flip(fl, l);
             proposals += l - l0 + 1;
             ++accepts;
             l0 = l + 1;
@@ -579,9 +622,34 @@ struct Engine : SliceState<C::JW> {
         }
         flush();
         proposals += L - l0;
-        if (w == next_rec) {
-          max_drift = fmax(max_drift, recompute(ws, true));
-          next_rec += d.recompute_every;
+        const bool retry = nonpos != np0 && attempt == 0;
+        attempt = retry;
+        if (retry) {  // back to the sweep's starting state
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+            if ((fl[jj] >> lane) & 1) set_field(jj, -sv[jj]);
+          });
+          proposals = pr0;
+          accepts = acc0;
+          nonpos = np0;
+          err = err0;
+          ++recoveries;
+        }
+        if (retry || w == next_rec) {
+          const double dr = recompute(ws, !retry);
+          if (!retry) {
+            max_drift = fmax(max_drift, dr);
+            if (d.drift_limit > 0.0 && !(dr <= d.drift_limit)) {
+              if (rec_every > 1)
+                rec_every >>= 1;
+              else
+                err = 1;
+            }
+            next_rec += rec_every;
+          }
+        }
+        if (retry) {
+          --w;
+          continue;
         }
         if (C::ACC && w >= d.n_warmup) {
           const int64_t m = w - d.n_warmup;
@@ -709,6 +777,11 @@ struct Engine : SliceState<C::JW> {
       st->nonpositive += nonpos;
       st->error |= err;
       st->max_drift = fmax(st->max_drift, max_drift);
+      st->recoveries += recoveries;
+      if (d.op == OP_SWEEPS) {
+        st->next_rec = next_rec;
+        st->rec_every = rec_every;
+      }
     }
     __syncthreads();
   }
@@ -755,9 +828,9 @@ template <class F>
 static const KernelInfo* each_kernel(F&& f) {
   for (const auto& k : kKernels)
     if (f(k)) return &k;
-  const KernelInfo* lists[2] = {nullptr, nullptr};
-  const int counts[2] = {window_kernels(&lists[0]), global_kernels(&lists[1])};
-  for (int l = 0; l < 2; ++l)
+  const KernelInfo* lists[3] = {nullptr, nullptr, nullptr};
+  const int counts[3] = {window_kernels(&lists[0]), global_kernels(&lists[1]), window_global_kernels(&lists[2])};
+  for (int l = 0; l < 3; ++l)
     for (int i = 0; i < counts[l]; ++i)
       if (f(lists[l][i])) return &lists[l][i];
   return nullptr;

@@ -69,11 +69,11 @@ struct EngineG : SliceState<C::JW> {
   __device__ __forceinline__ void set_field(int jj, int s) { Slices::set_field(jj, s, d.dflip_p, d.dflip_m); }
   __device__ __forceinline__ void flip_field(int l) { Slices::flip_field(l, lane, d.dflip_p, d.dflip_m); }
 
-  // Stores of every wave to G visible to the loads of every wave.
-  __device__ __forceinline__ void publish() {
-    __threadfence();
-    __syncthreads();
-  }
+  // Stores of every wave to G visible to the loads of every wave: the
+  // workgroup-scope release/acquire of the barrier suffices (the waves share
+  // the CU's caches); a device-scope fence would write back and invalidate
+  // the whole L2 each time.
+  __device__ __forceinline__ void publish() { __syncthreads(); }
 
   __device__ __forceinline__ int scan(int l0, const double (&uv)[JW], double& fu, double& fd, int64_t& nonpos,
                                       int64_t& err) const {
@@ -185,6 +185,15 @@ struct EngineG : SliceState<C::JW> {
     kb = 0;
   }
 
+  // Test hook: the diagonal copies the ratios read times x (1 leaves them
+  // unchanged, NaN poisons them).
+  __device__ __forceinline__ void scale_diag(double x) {
+    static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+      dgu[jj] *= x;
+      dgd[jj] *= x;
+    });
+  }
+
   __device__ __forceinline__ void diag_from_memory() {
     static_for<JW>([&](auto jj) __attribute__((always_inline)) {
       const int m = lane + 64 * jj;
@@ -283,7 +292,16 @@ struct EngineG : SliceState<C::JW> {
       if (tid == 0) {
         st->proposals = st->accepts = st->nonpositive = st->error = 0;
         st->max_drift = 0.0;
+        st->recoveries = 0;
       }
+    }
+    // recompute schedule: every recompute_every sweeps, or with a drift limit
+    // the (possibly shortened) schedule a previous launch of the chain left
+    int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+    int rec_every = d.recompute_every;
+    if (d.drift_limit > 0.0 && !(flags & F_ZERO_ACC) && st->rec_every > 0) {
+      next_rec = st->next_rec;
+      rec_every = st->rec_every;
     }
     for (int i = tid; i < 2 * LT; i += C::NTH) {
       const int s = i / LT, k = i % LT;
@@ -307,6 +325,7 @@ struct EngineG : SliceState<C::JW> {
 
     int64_t proposals = 0, accepts = 0, nonpos = 0, err = 0;
     double max_drift = 0.0;
+    int recoveries = 0;
 
     if (d.op == OP_SWEEPS) {
       // running bin sums, loaded on entry to a bin and stored when it is left
@@ -314,8 +333,15 @@ struct EngineG : SliceState<C::JW> {
       double gacc = 0.0, nacc_u = 0.0, nacc_d = 0.0, dacc = 0.0;
       int64_t cur_bin = -1;
       const int64_t nm = d.n_measure, nb = d.n_bins;
-      int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+      // numeric recovery: a sweep whose scan saw a ratio that was not a
+      // positive number is repeated once, from its starting fields and a
+      // from-scratch Dyson solve; the repeat failing too leaves the error set
+      int attempt = 0;
       for (int64_t w = d.sweep_begin; w < d.sweep_end; ++w) {
+        uint64_t fl[JW];  // slices flipped in this sweep (uniform)
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) { fl[jj] = 0; });
+        const int64_t pr0 = proposals, acc0 = accepts, np0 = nonpos, err0 = err;
+        scale_diag((attempt ? +d.poison[1] : +d.poison[0]) == w + 1 ? __builtin_nan("") : 1.0);
         double uv[JW];
         {
           const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
@@ -329,6 +355,7 @@ struct EngineG : SliceState<C::JW> {
           append(l, fu, fd);
           if (kb >= kdepth) flush();
           flip_field(l);
+          mark_flip(fl, l);
           proposals += l - l0 + 1;
           ++accepts;
           l0 = l + 1;
@@ -336,9 +363,34 @@ struct EngineG : SliceState<C::JW> {
         }
         flush();
         proposals += L - l0;
-        if (w == next_rec) {
-          max_drift = fmax(max_drift, recompute(true));
-          next_rec += d.recompute_every;
+        const bool retry = nonpos != np0 && attempt == 0;
+        attempt = retry;
+        if (retry) {  // back to the sweep's starting state
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) {
+            if ((fl[jj] >> lane) & 1) set_field(jj, -sv[jj]);
+          });
+          proposals = pr0;
+          accepts = acc0;
+          nonpos = np0;
+          err = err0;
+          ++recoveries;
+        }
+        if (retry || w == next_rec) {
+          const double dr = recompute(!retry);
+          if (!retry) {
+            max_drift = fmax(max_drift, dr);
+            if (d.drift_limit > 0.0 && !(dr <= d.drift_limit)) {
+              if (rec_every > 1)
+                rec_every >>= 1;
+              else
+                err = 1;
+            }
+            next_rec += rec_every;
+          }
+        }
+        if (retry) {
+          --w;
+          continue;
         }
         if (w >= d.n_warmup) {
           const int64_t m = w - d.n_warmup;
@@ -409,6 +461,11 @@ struct EngineG : SliceState<C::JW> {
       st->nonpositive += nonpos;
       st->error |= err;
       st->max_drift = fmax(st->max_drift, max_drift);
+      st->recoveries += recoveries;
+      if (d.op == OP_SWEEPS) {
+        st->next_rec = next_rec;
+        st->rec_every = rec_every;
+      }
     }
     __syncthreads();
   }

@@ -29,7 +29,7 @@
 // wave 0 scans, publishes P and S, and all waves flush: two barriers per
 // window instead of one per accepted flip.
 #pragma once
-#include "hfqmc_device.h"
+#include "hfqmc_wscan.h"
 
 namespace hfqmc {
 
@@ -68,34 +68,6 @@ struct WSmem {
   int item;
 };
 
-typedef double wd4 __attribute__((ext_vector_type(4)));
-typedef float wf4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double bperm_d(int addr, double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// a[k] for a per-lane k in [0, 4).  The array is taken by value: a select
-// of element addresses would turn register arrays into scratch memory.
-struct D4 {
-  double v[4];
-};
-__device__ __forceinline__ double sel4(D4 a, int k) {
-  const double x = (k & 1) ? a.v[1] : a.v[0];
-  const double y = (k & 1) ? a.v[3] : a.v[2];
-  return (k & 2) ? y : x;
-}
-__device__ __forceinline__ D4 d4of(const double (&a)[4]) { return D4{{a[0], a[1], a[2], a[3]}}; }
-
-enum WinMode : int {
-  WM_METROPOLIS = 0,  // Metropolis decisions over the window's slices
-  WM_DYSON = 1,       // switch every slice's potential on from V = 0
-  WM_FORCE = 2,       // flip one given slice
-};
-
 template <class C>
 struct EngineW {
   static constexpr int LT = C::LT, RT = C::RT, NT = C::NT, JW = C::JW, RS = C::RS, TS = C::TS, GS = C::GS;
@@ -113,6 +85,7 @@ struct EngineW {
   ImpDesc d;
   // wave-0 counters
   int64_t accepts = 0, nonpos = 0, err = 0;
+  double px = 1.0;  // test hook: NaN poisons the blocks the sweep's decisions read
 
   __device__ __forceinline__ EngineW(WSmem<C>& s)
       : sm(s),
@@ -178,126 +151,21 @@ struct EngineW {
     });
   }
 
-  // Rank-one update of both window blocks and of Q for an accepted slice j
-  // with factors f_s.  The wave keeps B'_s = B_s - 1 and Q'_s = Q_s - 1, so
-  // column j of B' is already B_s[:,j] - e_j: u_s = f_s B'_s[:,j],
-  // B'_s += u_s B_s[j,:], Q'_s += u_s Q_s[j,:] (rows of B and Q: the primed
-  // rows plus e_j).  Column j comes from lane 16q + j, row j from lane
-  // 16(j/4) + c, register j % 4 (a uniform choice: four branch leaves).
-  __device__ __forceinline__ void rank1(int j, double fu, double fd, double (&bu)[4], double (&bd)[4],
-                                        double (&qu)[4], double (&qd)[4]) {
-    const int src_col = ((lane & 48) | j) << 2;
-    const int src_row = (((j & 12) << 2) | c) << 2;
-    double rbu = 0.0, rbd = 0.0, rqu = 0.0, rqd = 0.0;
-    dispatch<4>(j & 3, [&](auto jr) __attribute__((always_inline)) {
-      constexpr int R = decltype(jr)::value;
-      rbu = bperm_d(src_row, bu[R]);
-      rbd = bperm_d(src_row, bd[R]);
-      rqu = bperm_d(src_row, qu[R]);
-      rqd = bperm_d(src_row, qd[R]);
-    });
-    double cu[4], cd[4];
-    static_for<4>([&](auto r) __attribute__((always_inline)) {
-      cu[r] = bperm_d(src_col, bu[r]);
-      cd[r] = bperm_d(src_col, bd[r]);
-    });
-    const double e = c == j ? 1.0 : 0.0;
-    rbu += e;
-    rbd += e;
-    rqu += e;
-    rqd += e;
-    static_for<4>([&](auto r) __attribute__((always_inline)) {
-      const double au = fu * cu[r], ad = fd * cd[r];
-      bu[r] = __builtin_fma(au, rbu, bu[r]);
-      bd[r] = __builtin_fma(ad, rbd, bd[r]);
-      qu[r] = __builtin_fma(au, rqu, qu[r]);
-      qd[r] = __builtin_fma(ad, rqd, qd[r]);
-    });
-  }
-
-  // Wave 0: the window's decisions.  Lane (q, c) with q == c/4 is the
-  // diagonal lane of window slice c (it holds B'_s[c][c] in register c % 4).
-  // Writes P_s (window coordinates) and S, |S| and the accepted slices in
-  // increasing order (4 bits each) to LDS.
+  // Wave 0: the window's decisions on the diagonal blocks of the published
+  // tile-row.
   __device__ __forceinline__ void scan(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out,
                                        int b) {
     const int base = 16 * ww;
-    double bu[4], bd[4], qu[4], qd[4];
-    {
-      const double* ru = sm.u.rows[b][0] + (4 * q) * RS + base + c;
-      const double* rd = sm.u.rows[b][1] + (4 * q) * RS + base + c;
-      static_for<4>([&](auto r) __attribute__((always_inline)) {
-        const double e = (4 * q + r == c) ? 1.0 : 0.0;
-        bu[r] = ru[r * RS] - e;
-        bd[r] = rd[r * RS] - e;
-        qu[r] = qd[r] = 0.0;
-      });
-    }
     const uint32_t fw0 = (uint32_t)(pick<JW>(fm, base >> 6) >> (base & 63)) & 0xFFFFu;
-    const bool dl = q == (c >> 2);
-    const int rr = c & 3;
-    const bool in = base + c < L;
     // factors as values: a conditional over the descriptor's members would
     // select their addresses and keep the whole engine in scratch memory
     const double fa = mode == WM_DYSON ? +d.dset_p : +d.dflip_p;  // sigma s_l = +1
     const double fb = mode == WM_DYSON ? +d.dset_m : +d.dflip_m;  // sigma s_l = -1
-    const int sn = (fw0 >> c) & 1;
-    const double du = sn ? fb : fa, dd = sn ? fa : fb;
     double u = 0.0;
     if (mode == WM_METROPOLIS) u = bperm_d(((base + c) & 63) << 2, u01(pick<JW>(xw, ww >> 2)));
-    uint32_t S = 0;
-    uint64_t slist = 0, badmask = 0;
-    int m = 0, l0 = 0;
-    for (;;) {
-      // R_s = 1 + (1 - G_s[c][c]) d_s = 1 - B'_s[c][c] d_s
-      const double Ru = __builtin_fma(-sel4(d4of(bu), rr), du, 1.0);
-      const double Rd = __builtin_fma(-sel4(d4of(bd), rr), dd, 1.0);
-      const double R = Ru * Rd;
-      const bool live = dl && in && c >= l0 && (mode != WM_FORCE || c == jf);
-      const uint64_t acc = __ballot(live && (mode != WM_METROPOLIS || u < R));
-      const double Fu = du * recip(Ru), Fd = dd * recip(Rd);
-      if (mode == WM_METROPOLIS) {
-        // R <= 0 (or not a number) among the slices this step rejects: every
-        // slice is rejected at most once, so the lanes can be collected
-        const uint64_t below = acc ? ((1ull << __builtin_ctzll(acc)) - 1) : ~0ull;
-        badmask |= __ballot(live && !(R > 0.0)) & below;
-      }
-      if (!acc) break;
-      const int lj = __builtin_ctzll(acc), j = lj & 15;
-      const double fu = readlane_d(Fu, lj), fd = readlane_d(Fd, lj);
-      if (mode == WM_FORCE) {
-        const double rv = readlane_d(R, lj);
-        if (lane == 0 && ratio_out) *ratio_out = rv;
-      }
-      rank1(j, fu, fd, bu, bd, qu, qd);
-      S |= 1u << j;
-      slist |= (uint64_t)j << (4 * m);
-      ++m;
-      l0 = j + 1;
-    }
-    // P_s = D_s Q_s: row i scaled by the factor of slice i if accepted, else 0
-    double* pu = sm.pb[0] + (4 * q) * TS + c;
-    double* pd = sm.pb[1] + (4 * q) * TS + c;
-    static_for<4>([&](auto r) __attribute__((always_inline)) {
-      const int i = 4 * q + r;
-      const int si = (fw0 >> i) & 1;
-      const bool acc_i = (S >> i) & 1;
-      const double fu_i = si ? fb : fa, fd_i = si ? fa : fb;
-      const double e = i == c ? 1.0 : 0.0;
-      pu[r * TS] = acc_i ? fu_i * (qu[r] + e) : 0.0;
-      pd[r * TS] = acc_i ? fd_i * (qd[r] + e) : 0.0;
-    });
-    if (mode == WM_METROPOLIS) {
-      accepts += m;
-      nonpos += __builtin_popcountll(badmask);
-      if (badmask) err = 1;
-    }
-    if (lane == 0) {
-      sm.win[0] = S;
-      sm.win[1] = (uint32_t)m;
-      sm.win[2] = (uint32_t)slist;
-      sm.win[3] = (uint32_t)(slist >> 32);
-    }
+    win_scan<TS>(sm.u.rows[b][0] + (4 * q) * RS + base + c, sm.u.rows[b][1] + (4 * q) * RS + base + c, RS, lane, q,
+                 c, base, L, fw0, fa, fb, mode, jf, u, px, ratio_out, sm.pb[0], sm.pb[1], sm.win, accepts, nonpos,
+                 err);
   }
 
   // Every wave: G_s += (G_s[:,S] - E_S) P_s[S,S] G_s[S,:] on its tiles.
@@ -369,7 +237,8 @@ struct EngineW {
     });
   }
 
-  // One window on every wave.  Returns the accepted slice mask.
+  // One window on every wave.  Returns 1 if a ratio of the window's scan was
+  // not a positive number (the same on every thread), else 0.
   __device__ __forceinline__ uint32_t window(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out) {
     refresh_ids();
     const int b = buf;
@@ -380,7 +249,8 @@ struct EngineW {
     if (wave == 0) scan(ww, mode, jf, xw, ratio_out, b);
     __syncthreads();
     const uint32_t S = __builtin_amdgcn_readfirstlane(sm.win[0]);
-    const int m = __builtin_amdgcn_readfirstlane(sm.win[1]);
+    const uint32_t w1 = __builtin_amdgcn_readfirstlane(sm.win[1]);
+    const int m = (int)(w1 & 0xFFu);
     const uint64_t slist = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sm.win[2]) |
                            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(sm.win[3]) << 32);
     if (mode != WM_DYSON && S) {
@@ -395,8 +265,10 @@ struct EngineW {
       else
         flush<false>(ww, m, slist, b);
     }
-    return S;
+    return (w1 >> 8) & 1u;
   }
+
+
 
   // ---------------------------------------------------------------- measurement
   // Part of S_k = sum_l eps G[(l + k) mod L][l] (eps = -1 where l + k
@@ -538,7 +410,16 @@ struct EngineW {
       if (tid == 0) {
         st->proposals = st->accepts = st->nonpositive = st->error = 0;
         st->max_drift = 0.0;
+        st->recoveries = 0;
       }
+    }
+    // recompute schedule: every recompute_every sweeps, or with a drift limit
+    // the (possibly shortened) schedule a previous launch of the chain left
+    int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+    int rec_every = d.recompute_every;
+    if (d.drift_limit > 0.0 && !(flags & F_ZERO_ACC) && st->rec_every > 0) {
+      next_rec = st->next_rec;
+      rec_every = st->rec_every;
     }
     for (int i = tid; i < 2 * LT; i += C::NTH) {
       const int s = i / LT, k = i % LT;
@@ -588,7 +469,12 @@ struct EngineW {
     }
     int64_t proposals = 0;
     double max_drift = 0.0;
-    int64_t next_rec = d.sweep_begin + (d.recompute_every - 1 - d.sweep_begin % d.recompute_every);
+    // numeric recovery: a sweep whose scan saw a ratio that was not a
+    // positive number is repeated once, from its starting fields and a
+    // from-scratch Dyson solve; the repeat failing too leaves the error set
+    int attempt = 0, recoveries = 0;
+    uint64_t fm0[JW];
+    int64_t acc0 = 0, np0 = 0, err0 = 0;
 
     // pass state
     int64_t w = d.sweep_begin;  // sweep of the next Metropolis pass
@@ -613,6 +499,7 @@ struct EngineW {
       }
       int ww0 = 0, ww1 = (L + 15) >> 4, jf = 0;
       double* rout = nullptr;
+      px = 1.0;
       uint64_t xw[JW];
       static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = 0; });
       if (mode == WM_DYSON) {
@@ -624,17 +511,37 @@ struct EngineW {
         ww1 = ww0 + 1;
         jf = l & 15;
         rout = fratios + kf;
-      } else if (wave == 0) {
-        const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
-                                      (uint64_t)d.chain, d.seed, d.site);
-        static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = x.v[jj]; });
+      } else {
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) { fm0[jj] = fm[jj]; });
+        acc0 = accepts;
+        np0 = nonpos;
+        err0 = err;
+        px = (attempt ? +d.poison[1] : +d.poison[0]) == w + 1 ? __builtin_nan("") : 1.0;
+        if (wave == 0) {
+          const U64x4 x = philox4x64_10((uint64_t)lane, (uint64_t)(w + d.rng_offset), kPurposeSweep,
+                                        (uint64_t)d.chain, d.seed, d.site);
+          static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = x.v[jj]; });
+        }
       }
       // ---- the pass's windows
-      for (int ww = ww0; ww < ww1; ++ww) window(ww, mode, jf, xw, rout);
+      uint32_t bad = 0;
+      for (int ww = ww0; ww < ww1; ++ww) bad |= window(ww, mode, jf, xw, rout);
       // ---- after the pass
       bool measure = false;
       if (mode == WM_DYSON) {
-        if (drift) max_drift = fmax(max_drift, diag_tile_drift(dt));
+        if (drift) {
+          const double dr = diag_tile_drift(dt);
+          max_drift = fmax(max_drift, dr);
+          if (d.op != OP_RECOMPUTE) {
+            if (d.drift_limit > 0.0 && !(dr <= d.drift_limit)) {
+              if (rec_every > 1)
+                rec_every >>= 1;
+              else
+                err = 1;
+            }
+            next_rec += rec_every;
+          }
+        }
         if (d.op == OP_RECOMPUTE) break;
         measure = measure_after;
         measure_after = false;
@@ -642,11 +549,22 @@ struct EngineW {
       } else if (mode == WM_FORCE) {
         ++kf;
         mode = WM_METROPOLIS;
+      } else if (bad && attempt == 0) {  // repeat sweep w from a Dyson solve
+        static_for<JW>([&](auto jj) __attribute__((always_inline)) { fm[jj] = fm0[jj]; });
+        accepts = acc0;
+        nonpos = np0;
+        err = err0;
+        attempt = 1;
+        ++recoveries;
+        mode = WM_DYSON;
+        drift = false;
+        measure_after = false;
+        continue;
       } else {
+        attempt = 0;
         proposals += L;
         ++w;
         if (w - 1 == next_rec) {  // recompute first, then measure sweep w - 1
-          next_rec += d.recompute_every;
           mode = WM_DYSON;
           drift = true;
           measure_after = true;
@@ -757,6 +675,11 @@ struct EngineW {
       st->nonpositive += nonpos;
       st->error |= err;
       st->max_drift = fmax(st->max_drift, max_drift);
+      st->recoveries += recoveries;
+      if (sweeps) {
+        st->next_rec = next_rec;
+        st->rec_every = rec_every;
+      }
     }
     __syncthreads();
   }

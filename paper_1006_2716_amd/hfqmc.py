@@ -45,7 +45,7 @@ class Result(C.Structure):
         ("docc", C.c_double), ("docc_err", C.c_double),
         ("accept_rate", C.c_double), ("max_drift", C.c_double),
         ("proposals", C.c_int64), ("accepts", C.c_int64), ("nonpositive", C.c_int64),
-        ("status", C.c_int32),
+        ("status", C.c_int32), ("recoveries", C.c_int32),
     ]
 
 
@@ -76,6 +76,8 @@ def lib():
             "hfqmc_workspace_size": [_VP, C.POINTER(Problem), C.c_int32, C.POINTER(C.c_size_t)],
             "hfqmc_solve": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t, C.POINTER(Result)],
             "hfqmc_solve_static": [_VP, C.POINTER(Problem), C.c_int32, C.POINTER(Result)],
+            "hfqmc_set_drift_limit": [_VP, C.c_double],
+            "hfqmc_debug_poison": [_VP, C.c_int64, C.c_int64],
             "hfqmc_stage": [_VP, C.POINTER(Problem), C.c_int32, _VP, C.c_size_t],
             "hfqmc_run": [_VP],
             "hfqmc_collect": [_VP, C.POINTER(Result)],
@@ -258,7 +260,7 @@ class _Results:
                             bins=bins.copy(), fields=ff.copy(), n_up=r.n[0], n_dn=r.n[1], n_up_err=r.n_err[0],
                             n_dn_err=r.n_err[1], docc=r.docc, docc_err=r.docc_err, accept_rate=r.accept_rate,
                             max_drift=r.max_drift, proposals=r.proposals, accepts=r.accepts,
-                            nonpositive=r.nonpositive, status=r.status))
+                            nonpositive=r.nonpositive, status=r.status, recoveries=r.recoveries))
         return out
 
 
@@ -294,6 +296,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_drift_limit(self, limit: float):
+        """hfqmc_set_drift_limit: recompute-interval control (0 = off)."""
+        _check(lib().hfqmc_set_drift_limit(self.h, float(limit)), "hfqmc_set_drift_limit")
+
+    def debug_poison(self, sweep_a: int = -1, sweep_b: int = -1):
+        """hfqmc_debug_poison: NaN into G at the start of sweep_a's first
+        attempt and of sweep_b's repeated attempt (-1: never)."""
+        _check(lib().hfqmc_debug_poison(self.h, int(sweep_a), int(sweep_b)), "hfqmc_debug_poison")
 
     # ---------------------------------------------------------------- batch
     def workspace_size(self, problems) -> int:
