@@ -162,7 +162,7 @@ hfqmc_status hfqmc_solve(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t 
  * agree with a run that never failed up to rounding.
  *
  * Drift limit (per context; HFQMC_FP64 default 0 = off, HFQMC_MIXED default
- * 1e-6): a scheduled from-scratch recompute that finds max |G_updated -
+ * 1e-3): a scheduled from-scratch recompute that finds max |G_updated -
  * G_recomputed| over the diagonal 16 x 16 blocks above the limit halves the
  * interval to the next recompute (kept across the launches of a chain); if
  * the interval is already 1 sweep, the impurity ends HFQMC_ENUMERIC.  EINVAL

@@ -111,9 +111,10 @@ void* scratch_ptr(int device) {
 int padded_L(int L) { return (L + 15) / 16 * 16; }
 
 constexpr int kMaxDelay = 32;    // panel capacity of the delayed-update kernels
-// Default drift limit of HFQMC_MIXED contexts: fp32 products in the window
-// flush; far below the statistical errors of the estimators (1e-3 .. 1e-2).
-constexpr double kMixedDriftLimit = 1e-6;
+// Default drift limit of HFQMC_MIXED contexts (fp32 products in the window
+// flush drift by ~1e-4 per sweep at U up to 12): at or below the statistical
+// errors of the estimators over runs of thousands of sweeps.
+constexpr double kMixedDriftLimit = 1e-3;
 constexpr int kAuxStreams = 3;   // extra streams for concurrent kernel classes
 constexpr int kSrvStreams = 6;   // serving launch streams
 constexpr int kMaxChains = 64;   // independent chains per problem

@@ -116,6 +116,11 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Device memory seen as the global address space: loads and stores through
+// these pointers are global_* instructions, not flat ones (which also count
+// against the LDS wait counter).
+typedef __attribute__((address_space(1))) double gdouble;
+
 // Marks slice l in a uniform bit mask of JW words (slice m: word m / 64).
 template <int JW>
 __device__ __forceinline__ void mark_flip(uint64_t (&fl)[JW], int l) {

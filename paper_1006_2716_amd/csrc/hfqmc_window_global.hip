@@ -54,14 +54,14 @@ struct GWSmem {
 template <class C>
 struct EngineGW {
   static constexpr int LT = C::LT, NT = C::NT, JW = C::JW, CS = C::CS, RSS = C::RSS;
-  static constexpr int CH = 3;  // tiles per chunk of the flush
+  static constexpr int CH = NT;  // tiles per chunk of the flush: a whole tile-row in flight
 
   GWSmem<C>& sm;
   const int tid, wave, lane, q, c;
   uint64_t fm[JW];          // fields: bit set <=> s = -1 (uniform)
   int L = 0;
   ImpDesc d;
-  double* gm = nullptr;     // G_up, G_dn (LT x LT each, row-major), then the drift snapshot
+  gdouble* gm = nullptr;    // G_up, G_dn (LT x LT each, row-major), then the drift snapshot
   int64_t accepts = 0, nonpos = 0, err = 0;  // wave-0 counters
   double px = 1.0;          // test hook: NaN poisons the blocks the sweep's decisions read
 
@@ -79,7 +79,7 @@ struct EngineGW {
   // the whole L2 each time.
   __device__ __forceinline__ void publish() { __syncthreads(); }
 
-  __device__ __forceinline__ double* gs(int s) const { return gm + (size_t)s * LT * LT; }
+  __device__ __forceinline__ gdouble* gs(int s) const { return gm + (size_t)s * LT * LT; }
 
   // G = G0 of both spins: the antiperiodic matrix of the Weiss samples.
   __device__ __forceinline__ void set_weiss() {
@@ -95,7 +95,7 @@ struct EngineGW {
   // The diagonal 16 x 16 tiles of both spins, parked behind G (drift of the
   // next Dyson solve).
   __device__ __forceinline__ void save_diag_tiles() {
-    double* snap = gm + 2 * (size_t)LT * LT;
+    gdouble* snap = gm + 2 * (size_t)LT * LT;
     for (int idx = tid; idx < 2 * NT * 256; idx += C::NTH) {
       const int s = idx / (NT * 256), t = (idx / 256) % NT, i = (idx / 16) & 15, j = idx & 15;
       snap[idx] = gs(s)[(size_t)(16 * t + i) * LT + 16 * t + j];
@@ -105,7 +105,7 @@ struct EngineGW {
 
   // max |G_parked - G| over the diagonal tiles (uniform).
   __device__ __forceinline__ double diag_tile_drift() {
-    const double* snap = gm + 2 * (size_t)LT * LT;
+    const gdouble* snap = gm + 2 * (size_t)LT * LT;
     double dr = 0.0;
     for (int idx = tid; idx < 2 * NT * 256; idx += C::NTH) {
       const int s = idx / (NT * 256), t = (idx / 256) % NT, i = (idx / 16) & 15, j = idx & 15;
@@ -169,7 +169,7 @@ struct EngineGW {
       const double* pb = sm.pb[s];
       const double* cs = sm.u.w.cs[s];
       const double* rs = sm.u.w.rs[s];
-      double* g = gs(s) + (size_t)(16 * ti + 4 * q) * LT + c;
+      gdouble* g = gs(s) + (size_t)(16 * ti + 4 * q) * LT + c;
       __asm__ volatile("" : "+v"(g));  // addresses derived here, not hoisted out of the variants
       double av[K4], bv[K4];
       static_for<K4>([&](auto gi) __attribute__((always_inline)) {
@@ -186,7 +186,7 @@ struct EngineGW {
       static_for<(NT + CH - 1) / CH>([&](auto ch) __attribute__((always_inline)) {
         constexpr int T0 = decltype(ch)::value * CH;
         constexpr int TN = NT - T0 < CH ? NT - T0 : CH;
-        double* gc = g + 16 * T0;
+        gdouble* gc = g + 16 * T0;
         __asm__ volatile("" : "+v"(gc));
         wd4 acc[TN];
         static_for<TN>([&](auto u) __attribute__((always_inline)) {
@@ -245,7 +245,7 @@ struct EngineGW {
     const int sme = tid >= L, k = tid - sme * L;
     double S = 0.0;
     for (int s = 0; s < 2; ++s) {
-      const double* Gs = gs(s);
+      const gdouble* Gs = gs(s);
       for (int r0 = 0; r0 < L; r0 += C::RB) {
         const int r1 = r0 + C::RB < L ? r0 + C::RB : L;
         __syncthreads();
@@ -269,7 +269,7 @@ struct EngineGW {
     d = *desc;
     L = d.L;
     accepts = nonpos = err = 0;
-    gm = reinterpret_cast<double*>(ws + d.off_state);
+    gm = (gdouble*)(ws + d.off_state);  // the workspace is device memory
     const int flags = d.flags;
     const int NV = n_values(L);
     double* bins = reinterpret_cast<double*>(ws + d.off_bins);

@@ -3,9 +3,8 @@
 fp64 flushes reproduce the oracle's Sherman-Morrison chain up to rounding:
 same Philox stream, same decisions, so the field trajectories coincide and
 the observables agree element by element.  Mixed precision (fp32 products
-added into fp64 G) has no exact reference: its observables are compared
-statistically with the fp64 oracle and its drift against a from-scratch
-fp64 Dyson solve is bounded and reported.
+added into fp64 G) has no exact reference; its statistical comparison with
+the fp64 oracle is in test_gpu_zstatistics_configs.py.
 """
 import numpy as np
 import pytest
@@ -30,14 +29,6 @@ def _chain(L, U, mu, beta, seed, site, n_warmup, n_measure, n_bins=4, delay=1, h
 def ctx64():
     from paper_1006_2716_amd import hfqmc
     c = hfqmc.Context(0)
-    yield c
-    c.close()
-
-
-@pytest.fixture(scope="module")
-def ctx_mixed():
-    from paper_1006_2716_amd import hfqmc
-    c = hfqmc.Context(0, precision=hfqmc.MIXED)
     yield c
     c.close()
 
@@ -70,22 +61,3 @@ def test_delayed_fp64_full_headline_sample(ctx64):
     for i, r in zip(idx, ref):
         assert np.array_equal(gpu[i]["fields"], r["fields"])
         assert np.max(np.abs(gpu[i]["bins"] - r["bins"])) < 1e-9
-
-
-@pytest.mark.parametrize("L,delay", [(40, 8), (64, 16), (80, 32)])
-def test_mixed_precision_statistics(ctx_mixed, L, delay):
-    """fp32 products: observables within 4 sigma of the fp64 oracle; drift reported and bounded."""
-    print(f"mixed L={L} k={delay}", flush=True)
-    p = _chain(L, U=6.0, mu=0.3, beta=0.25 * L, seed=17, site=3, n_warmup=200, n_measure=3200, n_bins=32,
-               delay=delay, h=0.1)
-    g = ctx_mixed.solve([p])[0]
-    r = oracle.run([p])[0]
-    s = oracle.summarize(r["bins"], L)
-    for key in ("n_up", "n_dn", "docc"):
-        z = (g[key] - s[key]) / np.hypot(g[key + "_err"], s[key + "_err"])
-        assert abs(z) < 4.0, (key, z)
-    # fp32 rounding of the delayed products: G drifts from the fp64 Dyson
-    # solution between recomputes (~1e-4 for 50 sweeps); a loose sanity bound,
-    # the value itself is the reported precision cost
-    assert 0 < g["max_drift"] < 1e-2
-    print(f"  mixed L={L} k={delay}: max drift vs fp64 Dyson {g['max_drift']:.2e}")
