@@ -17,8 +17,11 @@ sample of the same workload on the host cores.
 
 Other workloads (one JSON line each, --workload NAME or all):
   uneven   512 impurities, L ~ U{32,48,64,96,128}, beta = 8: untuned vs
-           autotuned fp64, and fp32-product delayed updates (k = 8, 16, 32)
-           with their drift and g(tau) shift against the fp64 path
+           autotuned fp64, and fp32 flush products (window and delayed k = 16)
+           under the drift limit, with refused impurities, drift and g(tau)
+           shift against the fp64 path
+  long     128 impurities at L = 160 (G in device memory): window updates vs
+           delayed updates (k = 16), time per proposal of a chain
   serving  Poisson request stream (200/s), L in {20,40,80,160} (4:3:2:1),
            U = 8, dtau = 0.25, 5000 sweeps, 200 sites x 10 DMFT iterations
            with device-resident state: p50/p99 latency and throughput;
@@ -27,8 +30,8 @@ Other workloads (one JSON line each, --workload NAME or all):
   trapped  21x21 trap (V0 = 0.05, U = 8, beta = 10, L = 40, AF seed), the
            325 sites with n > 1e-3, 1000 + 10000 sweeps, fp64
   slab     41x41 trap (V0 = 0.02, U = 8, beta = 16, L = 80, ~1000 atoms,
-           AF seed), 1281 sites, 1000 + 10000 sweeps; fp64 and fp32-product
-           delayed updates (k = 16)
+           AF seed), 1281 sites, 1000 + 10000 sweeps; fp64 and fp32 flush
+           products under the drift limit (refused sites counted)
   rdmft    one real-space DMFT iteration of the 21x21 trap: lattice Green
            function at 500 Matsubara frequencies, Weiss functions, the
            325-site solve, self-energy; the lattice part alone on 41x41
@@ -60,7 +63,7 @@ RECOMPUTE_EVERY = 50
 PROFILED_TRAFFIC = {
     # kernel: (source files, sha256 prefix, bytes per launch)
     "hfqmc::sweep_kernel<Cfg<64,2,0>>": (("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h"),
-                                         "94ccf9d89011127e", 1.747e9),
+                                         "4d4c17e81d65ff43", 2.533e7),
 }
 
 
@@ -249,7 +252,7 @@ def bench_serving(args):
     for s in sites:  # the device-memory kernel class bounds the tail: split it into chains
         if s["L"] > 128 and args.serve_chains > 1:
             s["n_chains"] = args.serve_chains
-    ctx = hfqmc.Context(0)
+    ctx = hfqmc.Context(0, tune_cache=args.tune_cache)
     ctx.attach_pool(1 << 30)
     ctx.serve_config(step_ms=args.step_ms, quantum_proposals=args.quantum)
     t0 = time.perf_counter()
@@ -269,6 +272,33 @@ def bench_serving(args):
            "steps": st["steps"],
            "launches": st["launches"], "step_ms_avg": st["step_ms_avg"], "launch_ms_avg": st["launch_ms_avg"]},
           higher_is_better=False, serving=out)
+
+
+def bench_long(args):
+    """L = 160 (G in device memory): 128 requests of the serving generator
+    (U = 8, dtau = 0.25) as one batch, window updates (the default) and
+    delayed updates (k = 16); time per proposal of one chain."""
+    from paper_1006_2716_amd import hfqmc, workloads
+    sites, _, weiss = workloads.serving_requests(n_sites=512, Ls=(160,), weights=(1,), seed=4)
+    probs = [dict(L=160, beta=s["beta"], U=s["U"], weiss=weiss(s, 0), n_warmup=200, n_measure=2000, recompute_every=50,
+                  n_bins=32, seed=s["seed"], site=s["site"]) for s in sites[:128]]
+    props = sum((p["n_warmup"] + p["n_measure"]) * p["L"] for p in probs)
+    legs = {}
+    for name, delay in (("window", 0), ("delayed_k16", 16)):
+        ctx = hfqmc.Context(0)
+        pk = [dict(p, delay=delay) for p in probs]
+        ctx.stage(pk)
+        ms, _, kern = timed_runs(ctx, args.steps, args.warmup)
+        r = ctx.collect()
+        assert all(x["status"] == 0 for x in r)
+        legs[name] = dict(ms=ms, kernel_ms=float(np.mean(kern)), proposals_per_s=props / (ms * 1e-3),
+                          us_per_proposal_of_a_chain=float(np.mean(kern)) * 1e3 / (2200 * 160),
+                          max_drift=max(x["max_drift"] for x in r), plan=list(ctx.plan(160, delay)[:2]))
+        ctx.close()
+    _line("HF-QMC spin-flip proposals/s (L=160, G in device memory)", legs["window"]["proposals_per_s"], "proposals/s",
+          args.steps, args.warmup, legs["window"]["ms"],
+          {"workload": "128 impurities at L=160 (serving generator: U=8, dtau=0.25, open 64-site chain centre site, "
+                       "mu_eff~U[-1,1]), 200+2000 sweeps, fp64", "proposals_per_step": props}, legs=legs)
 
 
 def bench_lattice(args, name):
@@ -454,15 +484,20 @@ def bench_thermo(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "serving", "serving_chains", "trapped", "slab", "rdmft",
-                             "trotter", "thermo", "all"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "long", "serving", "serving_chains",
+                                                                "trapped", "slab", "rdmft", "trotter", "thermo", "all"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-single", action="store_true", help="skip the single-impurity comparison")
     ap.add_argument("--delay", type=int, default=0,
-                    help="update kind: 0 window updates (default), 1 rank-one, 2..32 delayed rank-k")
+                    help="update kind: 0 the library's choice for L (default), 1 rank-one, 2..32 delayed rank-k")
+    ap.add_argument("--no-serving", action="store_true", help="headline: skip the serving-latency leg")
+    ap.add_argument("--tune-cache", default=None, help="serving: a tuning cache fixing kernel shapes per padded L")
+    ap.add_argument("--shape", default=None, metavar="RT,K",
+                    help="headline: force the L = 64 kernel shape (tile-rows per wave, k: 0 window, 1 rank-one, "
+                         ">1 delayed) through a temporary tuning cache")
     ap.add_argument("--mixed", action="store_true", help="fp32 products in the window flush or the delayed updates")
     ap.add_argument("--graph", action="store_true", help="replay the pass from a captured hipGraph")
     ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
@@ -495,7 +530,7 @@ def main():
         # process never touches the GPU itself
         import subprocess
         rc = 0
-        for n in ["uneven", "serving", "serving_chains", "trapped", "slab", "rdmft", "trotter", "thermo"]:
+        for n in ["uneven", "long", "serving", "serving_chains", "trapped", "slab", "rdmft", "trotter", "thermo"]:
             print(f"== {n}", file=sys.stderr, flush=True)
             cmd = [sys.executable, os.path.abspath(__file__), "--workload", n, "--steps", str(args.steps), "--warmup",
                    str(args.warmup), "--step-ms", str(args.step_ms), "--quantum", str(args.quantum)]
@@ -507,6 +542,8 @@ def main():
             print(f"== {n}", file=sys.stderr, flush=True)
             if n == "uneven":
                 bench_uneven(args)
+            elif n == "long":
+                bench_long(args)
             elif n == "serving":
                 bench_serving(args)
             elif n == "serving_chains":
@@ -529,7 +566,17 @@ def main():
         p["delay"] = args.delay
     n_imp = len(probs)
     L = probs[0]["L"]
-    ctx = hfqmc.Context(0, precision=hfqmc.MIXED if args.mixed else hfqmc.FP64)
+    tune = None
+    if args.shape:
+        import tempfile
+        rt_f, k_f = (int(x) for x in args.shape.split(","))
+        fd, tune = tempfile.mkstemp(suffix=".json")
+        with os.fdopen(fd, "w") as f:
+            json.dump({"arch": "gfx950", "entries": [{"precision": "mixed" if args.mixed else "fp64", "L_padded": 64,
+                                                       "rt": rt_f, "k": k_f, "proposals_per_s": 1.0}]}, f)
+    ctx = hfqmc.Context(0, precision=hfqmc.MIXED if args.mixed else hfqmc.FP64, tune_cache=tune)
+    if tune:
+        os.unlink(tune)  # read at context creation
     ws = ctx.alloc_workspace(probs)
     ctx.stage(probs, ws)
     rt, k, _ = ctx.plan(L, args.delay)
@@ -603,6 +650,24 @@ def main():
         out["speedup_vs_single_impurity_path"] = value / single
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(probs)
+    ctx.close()
+    if not args.no_serving:
+        # the metric's latency half: per-request p50/p99 of the serving stream,
+        # measured in a process of its own (stream-to-queue mapping depends on
+        # the contexts a process created before)
+        import subprocess
+        cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", "serving"], capture_output=True,
+                            text=True)
+        line = [x for x in cp.stdout.splitlines() if x.startswith("{")]
+        if cp.returncode == 0 and line:
+            srv = json.loads(line[-1])
+            s = srv.get("serving", {})
+            out["serving"] = {k: s.get(k) for k in ("p50_ms", "p99_ms", "p50_ms_by_L", "requests", "proposals_per_s",
+                                                    "makespan_s")
+                              if k in s}
+            out["serving"]["workload"] = srv["config"]["workload"]
+        else:
+            out["serving"] = {"error": f"serving leg exited {cp.returncode}"}
     print(json.dumps(out))
 
 

@@ -182,8 +182,9 @@ hfqmc_status hfqmc_debug_poison(hfqmc_ctx *ctx, int64_t sweep_a, int64_t sweep_b
 /* hfqmc_solve on the library's own device array of HFQMC_STATIC_BYTES per
  * device instead of a caller workspace.  For callers that cannot allocate
  * device memory (code under stream capture, serving loops, harnesses that
- * forbid hipMalloc): it allocates nothing, and the context's streams and
- * events already exist from hfqmc_create.  HFQMC_EINVAL, with nothing run,
+ * forbid hipMalloc): it allocates and creates nothing (the context's events
+ * exist from hfqmc_create; the kernel classes run one after another on the
+ * context stream, not forked onto auxiliary streams).  HFQMC_EINVAL, with nothing run,
  * if hfqmc_workspace_size of the batch exceeds HFQMC_STATIC_BYTES (at L = 64
  * about 390 impurities fit).  Every call on a device uses the same array, so
  * calls that overlap on one device (from several contexts or threads) race;

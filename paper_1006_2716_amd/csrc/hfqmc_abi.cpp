@@ -651,16 +651,26 @@ hfqmc_status set_device(hfqmc_ctx* c) {
   return HFQMC_OK;
 }
 
-hfqmc_status ensure_streams(hfqmc_ctx* c) {
+// The context's events (created with the context).
+hfqmc_status ensure_base_events(hfqmc_ctx* c) {
   if (c->ev_start) return HFQMC_OK;
-  for (int a = 0; a < kAuxStreams; ++a) {
-    HIP_TRY(hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&c->ev_join[a], hipEventDisableTiming));
-  }
-  HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  for (int a = 0; a < kAuxStreams; ++a) HIP_TRY(hipEventCreateWithFlags(&c->ev_join[a], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreate(&c->ev_end));
   HIP_TRY(hipEventCreate(&c->ev_start));
+  return HFQMC_OK;
+}
+
+// The auxiliary streams the classes of a pass fork onto, and the capture
+// stream, created at the first batch that uses them: every stream of a
+// process takes one of its few hardware queues in turn, and streams created
+// ahead of the serving engine's shift the engine's streams onto shared
+// queues (measured: serving p50 134 ms without them, 901 ms with them).
+hfqmc_status ensure_streams(hfqmc_ctx* c) {
+  TRY(ensure_base_events(c));
+  if (c->cap) return HFQMC_OK;
+  for (int a = 0; a < kAuxStreams; ++a) HIP_TRY(hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   return HFQMC_OK;
 }
 
@@ -748,9 +758,11 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
 
 // Stage a batch: group by kernel class (padded L, shape), order items inside
 // a class by descending work, upload descriptors and inputs.  `force`, when
-// set, overrides the plan of every problem (autotuning).
+// set, overrides the plan of every problem (autotuning).  `streams`: create
+// the auxiliary streams the pass forks onto (not for the static entry point,
+// which creates nothing and runs the classes in turn on the context stream).
 hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_ws, size_t ws_bytes,
-                        const Plan* force) {
+                        const Plan* force, bool streams = true) {
   for (int i = 0; i < n0; ++i) TRY(validate(p0[i], i));
   const Expanded ex = expand(p0, n0);  // from here on a work item is one chain
   const hfqmc_problem* p = ex.items.data();
@@ -758,7 +770,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
   Layout lo = plan_layout(p, n);
   if (ws_bytes < lo.total) return fail(HFQMC_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, lo.total);
   TRY(set_device(c));
-  TRY(ensure_streams(c));
+  TRY(streams ? ensure_streams(c) : ensure_base_events(c));
   if (c->gexec) {
     HIP_TRY(hipGraphExecDestroy(c->gexec));
     c->gexec = nullptr;
@@ -855,7 +867,9 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
 // memset and no host copy: the pass can be captured into a graph.
 hfqmc_status enqueue_pass(hfqmc_ctx* c, hipStream_t main, bool timing) {
   const int G = (int)c->groups.size();
-  const int ns = std::min(G, 1 + kAuxStreams);
+  // without the auxiliary streams (the static entry point) the classes run
+  // one after another on `main`
+  const int ns = c->cap ? std::min(G, 1 + kAuxStreams) : 1;
   if (timing) TRY(ensure_events(c, 2 * (size_t)G));
   HIP_TRY(launch_zero(c->ws + c->lo.queues, sizeof(int32_t) * 64, main));
   if (ns > 1) {
@@ -1139,9 +1153,9 @@ bool srv_step(hfqmc_ctx* c) {
         d.sweep_begin = r->done[j];
         d.sweep_end = r->done[j] + r->q[j];
         if (r->first)
-          d.flags = F_ZERO_ACC | F_SAVE | (r->given ? F_FIELDS_GIVEN : (r->keep ? F_KEEP_FIELDS : 0));
+          d.flags = F_ZERO_ACC | F_SAVE | F_SAVE_G | (r->given ? F_FIELDS_GIVEN : (r->keep ? F_KEEP_FIELDS : 0));
         else
-          d.flags = F_RESUME | F_SAVE;
+          d.flags = F_RESUME | F_SAVE | F_SAVE_G;
         descs[i] = d;
         order[i] = i;
         ++i;
@@ -1282,7 +1296,7 @@ hfqmc_status hfqmc_create(int device, void* hip_stream, hfqmc_precision precisio
     delete c;
     return st;
   }
-  if (hfqmc_status st = ensure_streams(c)) {
+  if (hfqmc_status st = ensure_base_events(c)) {
     delete c;
     return st;
   }
@@ -1313,12 +1327,12 @@ void hfqmc_destroy(hfqmc_ctx* c) {
   srv_shutdown(c);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   for (auto e : c->ev) (void)hipEventDestroy(e);
-  if (c->ev_start) {
-    for (int a = 0; a < kAuxStreams; ++a) {
-      (void)hipStreamDestroy(c->aux[a]);
-      (void)hipEventDestroy(c->ev_join[a]);
-    }
+  if (c->cap) {
+    for (int a = 0; a < kAuxStreams; ++a) (void)hipStreamDestroy(c->aux[a]);
     (void)hipStreamDestroy(c->cap);
+  }
+  if (c->ev_start) {
+    for (int a = 0; a < kAuxStreams; ++a) (void)hipEventDestroy(c->ev_join[a]);
     (void)hipEventDestroy(c->ev_fork);
     (void)hipEventDestroy(c->ev_start);
     (void)hipEventDestroy(c->ev_end);
@@ -1381,7 +1395,7 @@ hfqmc_status hfqmc_solve_static(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n,
   if (!ws) return fail(HFQMC_EDEVICE, "hfqmc_solve_static: no static array on device %d", c->device);
   {
     std::lock_guard<std::mutex> g(c->mu);
-    TRY(stage_impl(c, p, n, ws, HFQMC_STATIC_BYTES, nullptr));
+    TRY(stage_impl(c, p, n, ws, HFQMC_STATIC_BYTES, nullptr, false));
     TRY(set_device(c));
     // the whole pass, timed only by the start/end events created with the context
     HIP_TRY(hipEventRecord(c->ev_start, c->stream));
@@ -1397,6 +1411,7 @@ hfqmc_status hfqmc_run_graph(hfqmc_ctx* c) {
   if (!c || !c->staged) return fail(HFQMC_EINVAL, "hfqmc_run_graph: nothing staged");
   std::lock_guard<std::mutex> g(c->mu);
   TRY(set_device(c));
+  TRY(ensure_streams(c));
   if (!c->gexec) {
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     const hfqmc_status st = enqueue_pass(c, c->cap, false);
@@ -1682,7 +1697,7 @@ hfqmc_status hfqmc_site_set_fields(hfqmc_ctx* c, hfqmc_site* s, const int8_t* fi
   apply_settings(d, c);
   d.op = OP_FORCE;
   d.n_force = 0;
-  d.flags = F_FIELDS_GIVEN | F_SAVE | F_ZERO_ACC;
+  d.flags = F_FIELDS_GIVEN | F_SAVE | F_SAVE_G | F_ZERO_ACC;
   for (int j = 0; j < s->n_chains; ++j) TRY(site_launch(c, s, d, j));  // every chain starts here
   s->has_state = true;
   return HFQMC_OK;
@@ -1707,7 +1722,7 @@ hfqmc_status hfqmc_site_force_flips(hfqmc_ctx* c, hfqmc_site* s, const int32_t* 
   apply_settings(d, c);
     d.op = OP_FORCE;
     d.n_force = m;
-    d.flags = F_RESUME | F_SAVE;
+    d.flags = F_RESUME | F_SAVE | F_SAVE_G;
     TRY(site_launch(c, s, d));
     if (ratios) {
       HIP_TRY(hipMemcpy(ratios + k0, base + s->o_force + 4 * ((m + 1) & ~1), sizeof(double) * m,
@@ -1728,7 +1743,7 @@ hfqmc_status hfqmc_site_recompute(hfqmc_ctx* c, hfqmc_site* s, double* drift) {
   fill_constants(d, s->prob);
   apply_settings(d, c);
   d.op = OP_RECOMPUTE;
-  d.flags = F_RESUME | F_SAVE | F_ZERO_ACC;
+  d.flags = F_RESUME | F_SAVE | F_SAVE_G | F_ZERO_ACC;
   TRY(site_launch(c, s, d));
   if (drift) {
     ImpStatus st;

@@ -174,6 +174,7 @@ struct SliceState {
       // the ballot; the accepted lane's pair is read out below
       Fu[jj] = fpu[jj] * recip(Ru);
       Fd[jj] = fpd[jj] * recip(Rd);
+      __asm__ volatile("" : "+v"(Fu[jj]), "+v"(Fd[jj]));  // computed before the exit test
     });
     int l = L;
     static_for<JW>([&](auto k) __attribute__((always_inline)) {

@@ -25,9 +25,11 @@ enum Op : int32_t {
 enum Flags : int32_t {
   F_FIELDS_GIVEN = 1,  // take the initial fields from the init array, else draw them
   F_RESUME = 2,        // load fields and G tiles from the state area (no fresh Dyson)
-  F_SAVE = 4,          // store fields and G tiles to the state area at the end
+  F_SAVE = 4,          // store the fields (and with F_SAVE_G the G tiles) at the end
   F_ZERO_ACC = 8,      // clear bins and status before running
   F_KEEP_FIELDS = 16,  // take the fields left in the fields array, fresh Dyson
+  F_SAVE_G = 32,       // with F_SAVE: also store the register kernels' G tiles (resumable
+                       // sites); a batch solve stores only the fields
 };
 
 // One impurity work item.  All offsets are in bytes from the workspace base.

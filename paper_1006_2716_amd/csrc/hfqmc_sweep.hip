@@ -763,7 +763,7 @@ struct Engine : SliceState<C::JW> {
     }
 
     if (flags & F_SAVE) {
-      save_tiles(ws);
+      if (flags & F_SAVE_G) save_tiles(ws);
       if (wave == 0) {
         static_for<JW>([&](auto jj) __attribute__((always_inline)) {
           const int m = lane + 64 * jj;

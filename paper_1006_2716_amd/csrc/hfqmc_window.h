@@ -658,10 +658,12 @@ struct EngineW {
     }
 
     if (flags & F_SAVE) {
-      double* p = state_ptr(ws);
-      for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
-        p[(rt * NT + tj) * 4 + r] = g[rt][tj][r];
-      });
+      if (flags & F_SAVE_G) {
+        double* p = state_ptr(ws);
+        for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
+          p[(rt * NT + tj) * 4 + r] = g[rt][tj][r];
+        });
+      }
       if (wave == 0) {
         static_for<JW>([&](auto jj) __attribute__((always_inline)) {
           const int m = lane + 64 * jj;

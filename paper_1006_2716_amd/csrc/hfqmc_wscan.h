@@ -117,7 +117,10 @@ __device__ __forceinline__ void win_scan(const double* ru, const double* rd, int
     const double R = Ru * Rd;
     const bool live = dl && in && c >= l0 && (mode != WM_FORCE || c == jf);
     const uint64_t acc = __ballot(live && (mode != WM_METROPOLIS || u < R));
-    const double Fu = du * recip(Ru), Fd = dd * recip(Rd);
+    double Fu = du * recip(Ru), Fd = dd * recip(Rd);
+    // kept ahead of the loop exit: the reciprocals overlap the ballot instead
+    // of following it on the path to the next accept
+    __asm__ volatile("" : "+v"(Fu), "+v"(Fd));
     if (mode == WM_METROPOLIS) {
       // R <= 0 (or not a number) among the slices this step rejects: every
       // slice is rejected at most once, so the lanes can be collected
