@@ -258,7 +258,20 @@ struct EngineG : SliceState<C::JW> {
       for (int r0 = 0; r0 < L; r0 += C::RB) {
         const int r1 = r0 + C::RB < L ? r0 + C::RB : L;
         __syncthreads();
-        for (int idx = tid; idx < (r1 - r0) * LT; idx += C::NTH) sm.u.rows[idx] = Gs[(size_t)r0 * LT + idx];
+        {  // every load of a thread in flight before its first LDS store
+          constexpr int NR = (C::RB * LT + C::NTH - 1) / C::NTH;
+          const int n = (r1 - r0) * LT;
+          const double* src = Gs + (size_t)r0 * LT;
+          double v[NR];
+          static_for<NR>([&](auto u) __attribute__((always_inline)) {
+            const int idx = tid + u * C::NTH;
+            v[u] = idx < n ? src[idx] : 0.0;
+          });
+          static_for<NR>([&](auto u) __attribute__((always_inline)) {
+            const int idx = tid + u * C::NTH;
+            if (idx < n) sm.u.rows[idx] = v[u];
+          });
+        }
         __syncthreads();
         if (tid < 2 * L && sme == s) {
           const double* R = sm.u.rows;

@@ -54,7 +54,7 @@ struct GWSmem {
 template <class C>
 struct EngineGW {
   static constexpr int LT = C::LT, NT = C::NT, JW = C::JW, CS = C::CS, RSS = C::RSS;
-  static constexpr int CH = NT;  // tiles per chunk of the flush: a whole tile-row in flight
+  static constexpr int CH = (NT + 1) / 2;  // tiles per chunk of the flush: half a tile-row in flight
 
   GWSmem<C>& sm;
   const int tid, wave, lane, q, c;
@@ -121,16 +121,31 @@ struct EngineGW {
   }
 
   // Column strip G_s[:,W] and row strip G_s[W,:] of window ww into LDS.
+  // With 64 threads per tile-row, a strip of one spin is exactly four
+  // elements per thread at compile-time offsets; every load of a thread is
+  // issued before its first LDS store (a loop of load-then-store pairs would
+  // wait one memory round trip per element).
+  static_assert(16 * C::LT == 4 * C::NTH, "one tile-row per wave");
   __device__ __forceinline__ void stage_strips(int ww) {
     const int base = 16 * ww;
-    for (int idx = tid; idx < 2 * LT * 16; idx += C::NTH) {
-      const int s = idx / (LT * 16), i = (idx >> 4) % LT, j = idx & 15;
-      sm.u.w.cs[s][i * CS + j] = gs(s)[(size_t)i * LT + base + j];
-    }
-    for (int idx = tid; idx < 2 * 16 * LT; idx += C::NTH) {
-      const int s = idx / (16 * LT), i = (idx / LT) & 15, j = idx % LT;
-      sm.u.w.rs[s][i * RSS + j] = gs(s)[(size_t)(base + i) * LT + j];
-    }
+    constexpr int RSTEP = C::NTH / 16;  // column-strip rows per step
+    const int ci = tid >> 4, cj = tid & 15;            // column strip: row ci + RSTEP v, column cj
+    const int ri = tid / LT, rj = tid - (tid / LT) * LT;  // row strip: row ri + 4 v, column rj
+    const gdouble* pc = gm + (size_t)ci * LT + base + cj;
+    const gdouble* pr = gm + (size_t)(base + ri) * LT + rj;
+    double vc[2][4], vr[2][4];
+    static_for<2>([&](auto s) __attribute__((always_inline)) {
+      static_for<4>([&](auto v) __attribute__((always_inline)) {
+        vc[s][v] = pc[(size_t)s * LT * LT + (size_t)v * RSTEP * LT];
+        vr[s][v] = pr[(size_t)s * LT * LT + (size_t)v * 4 * LT];
+      });
+    });
+    static_for<2>([&](auto s) __attribute__((always_inline)) {
+      static_for<4>([&](auto v) __attribute__((always_inline)) {
+        sm.u.w.cs[s][(ci + v * RSTEP) * CS + cj] = vc[s][v];
+        sm.u.w.rs[s][(ri + 4 * v) * RSS + rj] = vr[s][v];
+      });
+    });
     __syncthreads();
   }
 
@@ -239,6 +254,21 @@ struct EngineGW {
     return (w1 >> 8) & 1u;
   }
 
+  // n consecutive doubles from device memory into the row buffer, all loads
+  // of a thread in flight before its first store.
+  static constexpr int NR = (C::RB * LT + C::NTH - 1) / C::NTH;
+  __device__ __forceinline__ void stage_rows(const gdouble* src, int n) {
+    double v[NR];
+    static_for<NR>([&](auto u) __attribute__((always_inline)) {
+      const int idx = tid + u * C::NTH;
+      v[u] = idx < n ? src[idx] : 0.0;
+    });
+    static_for<NR>([&](auto u) __attribute__((always_inline)) {
+      const int idx = tid + u * C::NTH;
+      if (idx < n) sm.u.rows[idx] = v[u];
+    });
+  }
+
   // g_s(tau_k) sums S_k = sum_l eps G_s[(l+k) mod L][l], staged through LDS
   // in blocks of rows; thread t = s*L + k returns S_k / L.
   __device__ __forceinline__ double green_sums() {
@@ -249,7 +279,7 @@ struct EngineGW {
       for (int r0 = 0; r0 < L; r0 += C::RB) {
         const int r1 = r0 + C::RB < L ? r0 + C::RB : L;
         __syncthreads();
-        for (int idx = tid; idx < (r1 - r0) * LT; idx += C::NTH) sm.u.rows[idx] = Gs[(size_t)r0 * LT + idx];
+        stage_rows(Gs + (size_t)r0 * LT, (r1 - r0) * LT);
         __syncthreads();
         if (tid < 2 * L && sme == s) {
           const double* R = sm.u.rows;
