@@ -150,14 +150,15 @@ bool window_default(int LT) {
   return LT == 80 || LT == 96;
 }
 
-// Untuned tile-rows per wave of the window kernels: the flush is spread over
-// as many waves as the register file allows two impurities per CU up to 80
-// slices, one beyond.
+// Untuned tile-rows per wave of the window kernels, each the measured best
+// on 512 impurities of the chain workload at that L: 64 slices 2 tile-rows;
+// 80 slices 5 (156 ms against 166 with one tile-row per wave, 386 against
+// 464 ms on the slab); 96 slices 1 (211 against 246 ms with 3); 128 slices 4
+// (510 against 579 with 2 and 641 with 1, whose registers spill).
 int default_rt_window(int LT) {
   switch (LT) {
     case 64: return 2;
     case 80: return 5;
-    case 96: return 3;
     case 128: return 4;
     default: return 1;
   }

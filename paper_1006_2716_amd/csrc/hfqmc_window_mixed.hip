@@ -5,7 +5,8 @@
 namespace hfqmc {
 
 static const KernelInfo kWindowMixed[] = {
-    winfo<32, 1, 1>(), winfo<48, 1, 1>(), winfo<64, 2, 1>(), winfo<80, 5, 1>(), winfo<96, 3, 1>(), winfo<128, 4, 1>(),
+    winfo<32, 1, 1>(), winfo<48, 1, 1>(), winfo<64, 2, 1>(), winfo<80, 1, 1>(), winfo<80, 5, 1>(), winfo<96, 1, 1>(),
+    winfo<96, 3, 1>(), winfo<128, 4, 1>(),
 };
 
 int window_kernels_mixed(const KernelInfo** list) {
