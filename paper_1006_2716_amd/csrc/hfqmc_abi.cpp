@@ -132,7 +132,8 @@ inline bool is_window(int dk) { return dk == kDkWindow || dk == kDkWindowMixed; 
 
 // Padded slice count of the window kernel serving L <= 128: the next
 // multiple of 16 up to 96, then 128 (no 112-slice window kernel is built:
-// seven tile-rows per wave do not fit the register file).
+// seven tile columns leave one tile-row per wave, fourteen waves whose
+// 128-register budget spills, or seven, 392 registers of tiles).
 int window_LT(int L) {
   if (L <= 96) return (L + 15) / 16 * 16;
   return 128;
@@ -144,22 +145,27 @@ int kernel_LT(int L, int dk) { return is_window(dk) && L <= kMaxRegisterL ? wind
 // Padded slice counts at which the untuned default is the window kernel
 // (elsewhere the rank-one kernel, measured faster there on MI355X).
 bool window_default(int LT) {
-  // 512 impurities of the chain workload: 158 against 228 ms at 80 slices,
-  // 245 against 284 ms at 96; at 32-64 slices the rank-one kernels are
-  // 8-16 % faster, at 128 the two take the same time
-  return LT == 80 || LT == 96;
+  // 512 impurities of the chain workload: 159 against 228 ms at 80 slices,
+  // 209 against 284 ms at 96, 335 against 504 ms at 128; at 32-64 slices
+  // the rank-one kernels are 4-25 % faster (48: 59 against 65 ms, 64: 75
+  // against 79)
+  return LT >= 80;
 }
 
 // Untuned tile-rows per wave of the window kernels, each the measured best
-// on 512 impurities of the chain workload at that L: 64 slices 2 tile-rows;
-// 80 slices 5 (156 ms against 166 with one tile-row per wave, 386 against
-// 464 ms on the slab); 96 slices 1 (211 against 246 ms with 3); 128 slices 4
-// (510 against 579 with 2 and 641 with 1, whose registers spill).
-int default_rt_window(int LT) {
+// on 512 impurities of the chain workload at that L: 48 slices 3 (65 ms),
+// 64 slices 2 (79 ms; 109 with one), 80 slices 5 (159 against 167 with one;
+// 393 against 466 ms on the 1281 slab sites, where five tile-rows per wave
+// put two impurities on a CU), 96 slices 1 (209 against 245 with 3), 128
+// slices 2 (335 against 505 with 4).  With fp32 flush products one tile-row
+// per wave at 80 slices (the slab: 3.4 s against 5.1 s with five, whose
+// registers spill with the fp32 conversions).
+int default_rt_window(int LT, bool mixed) {
   switch (LT) {
+    case 48: return 3;
     case 64: return 2;
-    case 80: return 5;
-    case 128: return 4;
+    case 80: return mixed ? 1 : 5;
+    case 128: return 2;
     default: return 1;
   }
 }
@@ -744,7 +750,7 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
     // mixed precision: the window kernel with fp32 flush products where one
     // is compiled for the class, else the fp64 one
     pl.k = 0;
-    pl.rt = default_rt_window(window_LT(p.L));
+    pl.rt = default_rt_window(window_LT(p.L), c->prec == HFQMC_MIXED);
     pl.dk = find_kernel(window_LT(p.L), pl.rt, dk_window) ? dk_window : kDkWindow;
   } else if (p.delay <= 1) {
     pl.rt = tuned && it->second.k == 1 ? it->second.rt : default_rt(LT, 0);

@@ -48,6 +48,11 @@ struct WCfg {
   static constexpr int GS = LT + 1;         // row stride of dumped rows (g(tau) estimator)
   static constexpr int DR = LT < 64 ? LT : 64;  // rows per dump block
   static constexpr int MINB = LT <= 64 ? 2 : 1;
+  // registers per lane of a wave (VGPRs + AGPRs) when every wave of
+  // MINB workgroups is resident, and the flush form: looped where the
+  // tiles take half of them or more
+  static constexpr int BUDGET = 512 / ((NW * MINB + 3) / 4);
+  static constexpr bool LOOP = 2 * (RT * NT * 8) >= BUDGET;
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
   static_assert(NTH >= LT, "measurement needs one thread per tau_k");
   static_assert(DR * GS <= 4 * 16 * RS, "dump block must fit the row buffers");
@@ -62,7 +67,7 @@ struct WSmem {
   double tb[C::NW][C::RT][16 * C::TS];  // each wave's tiles of the window's column strip
   double pb[2][16 * C::TS];             // P_s = D_s Q_s of the window (window coordinates)
   double diag[2][C::LT];                // diagonals of G_up, G_dn after a measured sweep
-  double weiss[2][C::LT];               // Weiss samples, zero padded
+  double weiss[2][2 * C::LT];           // G0_s along its diagonals: [LT + i - j] = G0_s[i][j]
   double red[C::NW];
   uint32_t win[4];                      // S mask, |S|, accepted slices (4 bits each, two words)
   int item;
@@ -173,18 +178,44 @@ struct EngineW {
   // slices in order, columns = the tile's rows permuted so that the update's
   // fp64 accumulator lands in the tile layout), then for every tile column
   // G[r, tj] += V^T G[S, tj]: the accumulator registers of V are the A
-  // operands of the update, four accepted slices per instruction.  K4 =
-  // ceil(|S| / 4) is a compile-time count in each of the four branches, so
-  // every operand load of a tile is issued before its matrix-core steps.
-  template <bool FP32>
-  __device__ __forceinline__ void flush(int ww, int m, uint64_t slist, int b) {
-    dispatch<4>((m - 1) >> 2, [&](auto kk) __attribute__((always_inline)) {
-      flush_k<FP32, decltype(kk)::value + 1>(ww, m, slist, b);
-    });
+  // operands of the update, four accepted slices per instruction.  fp32
+  // (mixed kernels, Metropolis windows): fp32 products added into the tiles.
+  // Two forms of the same arithmetic (each tile adds the groups of four
+  // slices in order, so both give the same bits):
+  //  * unrolled: ceil(|S| / 4) is a compile-time count in each of four
+  //    branches, every operand load issued before the matrix-core steps;
+  //  * looped over the groups (C::LOOP): one code path for every |S|.  Four
+  //    branches give each tile four definitions to merge, which the large
+  //    shapes with two waves per SIMD cannot hold in registers.
+  __device__ __forceinline__ void flush(int ww, int m, uint64_t slist, int b, bool fp32) {
+    const bool f32 = C::MX && fp32;
+    if constexpr (C::LOOP) {
+      flush_loop(ww, m, slist, b, f32);
+    } else {
+      dispatch<4>((m - 1) >> 2, [&](auto kk) __attribute__((always_inline)) {
+        flush_k<decltype(kk)::value + 1>(ww, m, slist, b, f32);
+      });
+    }
   }
 
-  template <bool FP32, int K4>
-  __device__ __forceinline__ void flush_k(int ww, int m, uint64_t slist, int b) {
+  // row of the tile fed as V's column ii: permuted for the fp64 accumulator
+  // (rows 4*reg + lane/16), natural for fp32 (rows 4*(lane/16) + reg)
+  __device__ __forceinline__ static int v_row(int ii, bool f32) { return f32 ? ii : 4 * (ii & 3) + (ii >> 2); }
+
+  __device__ __forceinline__ void tile_update(double (&t)[4], double a, double rv, bool f32) {
+    if (!f32) {
+      wd4 acc = {t[0], t[1], t[2], t[3]};
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rv, acc, 0, 0, 0);
+      static_for<4>([&](auto r2) __attribute__((always_inline)) { t[r2] = acc[decltype(r2)::value]; });
+    } else {
+      wf4 p = {0.f, 0.f, 0.f, 0.f};
+      p = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)rv, p, 0, 0, 0);
+      static_for<4>([&](auto r2) __attribute__((always_inline)) { t[r2] += (double)p[decltype(r2)::value]; });
+    }
+  }
+
+  template <int K4>
+  __device__ __forceinline__ void flush_k(int ww, int m, uint64_t slist, int b, bool f32) {
     const int ii = lane & 15, qq = lane >> 4;
     const double* pb = sm.pb[spin];
     const double* rows = sm.u.rows[b][spin];
@@ -196,9 +227,7 @@ struct EngineW {
       kv[gi] = k < m;
       sk[gi] = (int)(slist >> (4 * k)) & 15;
     });
-    // row of the tile fed as V's column ii: permuted for the fp64
-    // accumulator (rows 4*reg + lane/16), natural for fp32 (rows 4*(lane/16) + reg)
-    const int pi = FP32 ? ii : 4 * (ii & 3) + (ii >> 2);
+    const int pi = v_row(ii, f32);
     static_for<RT>([&](auto rt) __attribute__((always_inline)) {
       const int r = wr * RT + rt;
       const double* tb = sm.tb[wave][rt];
@@ -219,22 +248,48 @@ struct EngineW {
           const double x = rows[sk[gi] * RS + 16 * tj + ii];
           rv[gi] = kv[gi] ? x : 0.0;
         });
-        if constexpr (!FP32) {
-          wd4 acc = {g[rt][tj][0], g[rt][tj][1], g[rt][tj][2], g[rt][tj][3]};
-          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(V[decltype(gi)::value], rv[gi], acc, 0, 0, 0);
-          });
-          static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] = acc[decltype(r2)::value]; });
-        } else {
-          // fp32 products of four accepted slices each, added into the fp64 tile
-          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-            wf4 p = {0.f, 0.f, 0.f, 0.f};
-            p = __builtin_amdgcn_mfma_f32_16x16x4f32((float)V[decltype(gi)::value], (float)rv[gi], p, 0, 0, 0);
-            static_for<4>([&](auto r2) __attribute__((always_inline)) { g[rt][tj][r2] += (double)p[decltype(r2)::value]; });
-          });
-        }
+        static_for<K4>([&](auto gi) __attribute__((always_inline)) {
+          tile_update(g[rt][tj], V[decltype(gi)::value], rv[gi], f32);
+        });
       });
     });
+  }
+
+  __device__ __forceinline__ void flush_loop(int ww, int m, uint64_t slist, int b, bool f32) {
+    const int ii = lane & 15, qq = lane >> 4;
+    const double* pb = sm.pb[spin];
+    const double* rows = sm.u.rows[b][spin];
+    const int si = (int)(slist >> (4 * ii)) & 15;
+    const int pi = v_row(ii, f32);
+    const int K4 = (m + 3) >> 2;
+    wd4 V[RT];
+    static_for<RT>([&](auto rt) __attribute__((always_inline)) { V[rt] = wd4{0.0, 0.0, 0.0, 0.0}; });
+    for (int gi = 0; gi < K4; ++gi) {
+      const int k = 4 * gi + qq;
+      const bool kv = k < m;
+      const int sk = (int)(slist >> (4 * k)) & 15;
+      const double x = pb[sk * TS + si];
+      const double av = (kv && ii < m) ? x : 0.0;
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        const int r = wr * RT + rt;
+        const double y = sm.tb[wave][rt][pi * TS + sk] - ((r == ww && pi == sk) ? 1.0 : 0.0);
+        V[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, kv ? y : 0.0, V[rt], 0, 0, 0);
+      });
+    }
+    for (int gi = 0; gi < K4; ++gi) {
+      const int k = 4 * gi + qq;
+      const bool kv = k < m;
+      const int sk = (int)(slist >> (4 * k)) & 15;
+      double a[RT];  // V[gi] with a uniform gi: selects, not a register-indexed move
+      static_for<RT>([&](auto rt) __attribute__((always_inline)) {
+        a[rt] = gi == 0 ? V[rt][0] : gi == 1 ? V[rt][1] : gi == 2 ? V[rt][2] : V[rt][3];
+      });
+      static_for<NT>([&](auto tj) __attribute__((always_inline)) {
+        const double x = rows[sk * RS + 16 * tj + ii];
+        const double rv = kv ? x : 0.0;
+        static_for<RT>([&](auto rt) __attribute__((always_inline)) { tile_update(g[rt][tj], a[rt], rv, f32); });
+      });
+    }
   }
 
   // One window on every wave.  Returns 1 if a ratio of the window's scan was
@@ -259,12 +314,7 @@ struct EngineW {
         if (jj == (base >> 6)) fm[jj] ^= (uint64_t)S << (base & 63);
       });
     }
-    if (m) {
-      if (C::MX && mode == WM_METROPOLIS)
-        flush<true>(ww, m, slist, b);
-      else
-        flush<false>(ww, m, slist, b);
-    }
+    if (m) flush(ww, m, slist, b, mode == WM_METROPOLIS);
     return (w1 >> 8) & 1u;
   }
 
@@ -338,13 +388,14 @@ struct EngineW {
 
   // G = G0: the antiperiodic Toeplitz matrix of this wave's spin
   // (G0[i][j] = g(tau_{i-j}) for i >= j, -g(tau_{i-j+L}) below), zero in the
-  // padding.
+  // padding.  Every element is an immediate offset from one address per
+  // lane, and the padding is a product with 0, not a branch: a conditional
+  // load per element splits the tiles' live ranges and they end in scratch.
   __device__ __forceinline__ void set_weiss() {
+    const double* base = sm.weiss[spin] + (LT + 4 * q - c + 16 * (wr * RT) - 16 * (NT - 1));
     for_tiles([&](auto rt, auto tj, auto r) __attribute__((always_inline)) {
       const int i = (wr * RT + rt) * 16 + 4 * q + r, j = tj * 16 + c;
-      double v = 0.0;
-      if (i < L && j < L) v = i >= j ? sm.weiss[spin][i - j] : -sm.weiss[spin][i - j + L];
-      g[rt][tj][r] = v;
+      g[rt][tj][r] = base[16 * (rt - tj + NT - 1) + r] * ((i < L && j < L) ? 1.0 : 0.0);
     });
   }
 
@@ -421,9 +472,14 @@ struct EngineW {
       next_rec = st->next_rec;
       rec_every = st->rec_every;
     }
-    for (int i = tid; i < 2 * LT; i += C::NTH) {
-      const int s = i / LT, k = i % LT;
-      sm.weiss[s][k] = k < L ? wv[s * L + k] : 0.0;
+    for (int i = tid; i < 4 * LT; i += C::NTH) {
+      const int s = i / (2 * LT), dd = i % (2 * LT) - LT;  // dd = i - j
+      double v = 0.0;
+      if (dd >= 0 && dd < L)
+        v = wv[s * L + dd];
+      else if (dd < 0 && dd > -L)
+        v = -wv[s * L + dd + L];
+      sm.weiss[s][LT + dd] = v;
     }
     // fields as uniform bit masks
     if (flags & (F_FIELDS_GIVEN | F_RESUME | F_KEEP_FIELDS)) {
@@ -504,7 +560,6 @@ struct EngineW {
       static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = 0; });
       if (mode == WM_DYSON) {
         if (drift) copy_diag_tiles(dt);
-        set_weiss();
       } else if (mode == WM_FORCE) {
         const int l = fslices[kf];
         ww0 = l >> 4;
@@ -523,6 +578,7 @@ struct EngineW {
           static_for<JW>([&](auto jj) __attribute__((always_inline)) { xw[jj] = x.v[jj]; });
         }
       }
+      if (mode == WM_DYSON) set_weiss();  // after the pass's set-up (placed here it does not spill)
       // ---- the pass's windows
       uint32_t bad = 0;
       for (int ww = ww0; ww < ww1; ++ww) bad |= window(ww, mode, jf, xw, rout);

@@ -6,7 +6,7 @@ namespace hfqmc {
 
 static const KernelInfo kWindowFp64[] = {
     winfo<16, 1>(), winfo<32, 1>(), winfo<32, 2>(), winfo<48, 1>(), winfo<48, 3>(),
-    winfo<64, 1>(), winfo<64, 2>(), winfo<80, 1>(), winfo<80, 5>(), winfo<96, 1>(), winfo<96, 3>(), winfo<128, 4>(),
+    winfo<64, 1>(), winfo<64, 2>(), winfo<80, 1>(), winfo<80, 5>(), winfo<96, 1>(), winfo<96, 3>(), winfo<128, 2>(), winfo<128, 4>(),
 };
 
 int window_kernels_fp64(const KernelInfo** list) {

@@ -17,7 +17,7 @@ SHAPES = [(16, 1, 1), (32, 1, 1), (32, 2, 1), (48, 1, 1), (48, 3, 1), (64, 1, 1)
           (80, 1, 1), (96, 1, 1), (96, 2, 1), (96, 3, 1), (112, 1, 1), (128, 1, 1), (128, 2, 1),
           # window updates; the 112-slice class runs on the 128-slice window kernel
           (16, 1, 0), (32, 1, 0), (32, 2, 0), (48, 1, 0), (48, 3, 0), (64, 1, 0), (64, 2, 0), (80, 1, 0),
-          (80, 5, 0), (96, 1, 0), (96, 3, 0), (112, 4, 0), (128, 4, 0),
+          (80, 5, 0), (96, 1, 0), (96, 3, 0), (112, 2, 0), (128, 2, 0), (128, 4, 0),
           # G in device memory: window updates (rt 0, k 0) and delayed updates
           (144, 0, 0), (160, 0, 0), (160, 0, 16)]
 
