@@ -342,6 +342,7 @@ struct Group {
   const KernelInfo* k;
   int LT, rt, dk;
   int first, count, grid;
+  int stream = 0;  // index into the pass's streams (0: the context stream)
 };
 
 // A batch with every problem split into its chains: item k runs chain
@@ -825,6 +826,31 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
     k = e;
   }
   if (groups.size() > 64) return fail(HFQMC_EINVAL, "too many kernel classes");
+  // Streams of the classes: longest expected class first, each onto the
+  // stream with the least expected work so far, so that a short class does
+  // not queue behind the longest one when there are more classes than
+  // streams (measured on the uneven batch: the 32-slice class after the
+  // 128-slice one made the pass 232 ms instead of 206).  Expected duration:
+  // the heaviest item, or the class's work spread over its resident items.
+  {
+    const int G = (int)groups.size();
+    const int ns = streams ? std::min(G, 1 + kAuxStreams) : 1;
+    std::vector<double> est(G);
+    for (int g = 0; g < G; ++g) {
+      double sum = 0.0;
+      for (int i = groups[g].first; i < groups[g].first + groups[g].count; ++i) sum += cost(idx[i]);
+      est[g] = std::max(cost(idx[groups[g].first]), sum / groups[g].grid);
+    }
+    std::vector<int> by(G);
+    for (int g = 0; g < G; ++g) by[g] = g;
+    std::stable_sort(by.begin(), by.end(), [&](int a, int b) { return est[a] > est[b]; });
+    std::vector<double> load(ns, 0.0);
+    for (int g : by) {
+      const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      groups[g].stream = st;
+      load[st] += est[g];
+    }
+  }
 
   // host image of the input region [descs, status)
   std::vector<uint8_t> img(lo.status, 0);
@@ -888,7 +914,8 @@ hfqmc_status enqueue_pass(hfqmc_ctx* c, hipStream_t main, bool timing) {
   int* queues = reinterpret_cast<int*>(c->ws + c->lo.queues);
   for (int gi = 0; gi < G; ++gi) {
     const Group& gr = c->groups[gi];
-    hipStream_t st = gi % ns == 0 ? main : c->aux[gi % ns - 1];
+    const int si = gr.stream % ns;
+    hipStream_t st = si == 0 ? main : c->aux[si - 1];
     if (timing) HIP_TRY(hipEventRecord(c->ev[2 * gi], st));
     HIP_TRY(launch_sweep(gr.k, gr.grid, st, descs, order + gr.first, gr.count, queues + gi, c->ws));
     if (timing) HIP_TRY(hipEventRecord(c->ev[2 * gi + 1], st));
@@ -1547,7 +1574,16 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
       cands.push_back({0, kDkWindow, 0});
     if (find_kernel(LT, 0, 1))  // the global-memory kernel (fp64 flushes in either precision)
       for (int k : {4, 8, 16}) cands.push_back({0, 1, k});
+    // the untuned default of the class, timed like the others (added when
+    // it is not a candidate: the fp64 window kernel serving a mixed context)
+    c->tune.erase(LT);
+    hfqmc_problem q0 = sample[0];
+    q0.delay = 0;
+    const Plan def = plan_for(c, q0);
+    auto same = [](const Plan& a, const Plan& b) { return a.rt == b.rt && a.dk == b.dk && a.k == b.k; };
+    if (std::none_of(cands.begin(), cands.end(), [&](const Plan& x) { return same(x, def); })) cands.push_back(def);
     TuneEntry best{prec_name(c->prec), LT, 0, 0, -1.0, ""};
+    TuneEntry dflt = best;
     std::string measured;
     for (const Plan& pl : cands) {
       TRY(stage_impl(c, sample.data(), (int)sample.size(), d_ws, ws_bytes, &pl));
@@ -1565,7 +1601,12 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
       std::snprintf(buf, sizeof buf, "%s[%d, %d, %.6g]", measured.empty() ? "" : ", ", pl.rt, pl.k, rate);
       measured += buf;
       if (rate > best.rate) best = {prec_name(c->prec), LT, pl.rt, pl.k, rate, ""};
+      if (same(pl, def)) dflt = {prec_name(c->prec), LT, pl.rt, pl.k, rate, ""};
     }
+    // shortened chains rank close shapes by noise and by their first sweeps:
+    // the default (the best of full-length runs) stays unless a shape beats
+    // it by 5 % or more
+    if (dflt.rate > 0.0 && best.rate < 1.05 * dflt.rate) best = dflt;
     best.measured = measured;
     c->tune[LT] = best;
     bool replaced = false;

@@ -112,6 +112,9 @@ def test_autotuner_picks_measured_shape_and_persists(tmp_path):
         assert set(ents) == {32, 48, 64}
         for LT, e in ents.items():
             assert e["k"] in (0, 1, 4, 8, 16, 32) and e["proposals_per_s"] > 0
+            # the fastest shape, or the untuned default within 5 % of it
+            rates = [m[2] for m in e["measured"]]
+            assert e["proposals_per_s"] in rates and e["proposals_per_s"] * 1.05 >= max(rates)
             rt, k, rate = c.plan(LT, 0)
             assert (rt, k) == (e["rt"], e["k"]) and rate > 0
         # a new context reads the same plan from the cache
