@@ -57,7 +57,12 @@ struct EngineGW {
   static constexpr int CH = (NT + 1) / 2;  // tiles per chunk of the flush: half a tile-row in flight
 
   GWSmem<C>& sm;
-  const int tid, wave, lane, q, c;
+  // thread and wave indices; refresh_ids() re-derives them behind an opaque
+  // asm statement at the start of every window and measurement, so the
+  // addresses built from them are recomputed there instead of hoisted out of
+  // the sweep loop into long-lived registers (hoisted, they pushed the wave-0
+  // scan into scratch: 168 VGPRs + 97 spilled, now 128 and none)
+  int tid, wave, lane, q, c;
   uint64_t fm[JW];          // fields: bit set <=> s = -1 (uniform)
   int L = 0;
   ImpDesc d;
@@ -78,6 +83,18 @@ struct EngineGW {
   // the CU's caches); a device-scope fence would write back and invalidate
   // the whole L2 each time.
   __device__ __forceinline__ void publish() { __syncthreads(); }
+
+  __device__ __forceinline__ void refresh_ids() {
+    int t = threadIdx.x;
+    __asm__ volatile("" : "+v"(t));
+    tid = t;
+    lane = t & 63;
+    q = (t >> 4) & 3;
+    c = t & 15;
+    int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    __asm__ volatile("" : "+s"(w));
+    wave = w;
+  }
 
   __device__ __forceinline__ gdouble* gs(int s) const { return gm + (size_t)s * LT * LT; }
 
@@ -166,18 +183,13 @@ struct EngineGW {
   // every tile column G_s[rows, tj] += V^T G_s[S, tj] (fp64 accumulator rows
   // fed permuted so that it lands in the layout lane (q, c), register r =
   // row 4q + r, column c), tile by tile from and back to device memory.
-  // K4 = ceil(|S| / 4) matrix-core steps per tile.
-  template <int K4>
-  __device__ __forceinline__ void flush_k(int ww, int m, uint64_t slist) {
+  // The ceil(|S| / 4) matrix-core steps of a tile run as a loop over the
+  // groups of four accepted slices: one code path for every |S| (a branch
+  // per group count, each unrolled, spilled 150 registers per lane here).
+  __device__ __forceinline__ void flush(int ww, int m, uint64_t slist) {
     const int ii = lane & 15, qq = lane >> 4;
     const int si = (int)(slist >> (4 * ii)) & 15;
-    int sk[K4];
-    bool kv[K4];
-    static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-      const int k = 4 * gi + qq;
-      kv[gi] = k < m;
-      sk[gi] = (int)(slist >> (4 * k)) & 15;
-    });
+    const int K4 = (m + 3) >> 2;
     const int pi = 4 * (ii & 3) + (ii >> 2);
     const int ti = wave;
     for (int s = 0; s < 2; ++s) {
@@ -185,18 +197,16 @@ struct EngineGW {
       const double* cs = sm.u.w.cs[s];
       const double* rs = sm.u.w.rs[s];
       gdouble* g = gs(s) + (size_t)(16 * ti + 4 * q) * LT + c;
-      __asm__ volatile("" : "+v"(g));  // addresses derived here, not hoisted out of the variants
-      double av[K4], bv[K4];
-      static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-        const double x = pb[sk[gi] * CS + si];
-        const double y = cs[(16 * ti + pi) * CS + sk[gi]] - ((ti == ww && pi == sk[gi]) ? 1.0 : 0.0);
-        av[gi] = (kv[gi] && ii < m) ? x : 0.0;
-        bv[gi] = kv[gi] ? y : 0.0;
-      });
+      __asm__ volatile("" : "+v"(g));  // addresses derived here, not hoisted out of the spin loop
       wd4 V = {0.0, 0.0, 0.0, 0.0};
-      static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-        V = __builtin_amdgcn_mfma_f64_16x16x4f64(av[gi], bv[gi], V, 0, 0, 0);
-      });
+      for (int gi = 0; gi < K4; ++gi) {
+        const int k = 4 * gi + qq;
+        const bool kv = k < m;
+        const int sk = (int)(slist >> (4 * k)) & 15;
+        const double x = pb[sk * CS + si];
+        const double y = cs[(16 * ti + pi) * CS + sk] - ((ti == ww && pi == sk) ? 1.0 : 0.0);
+        V = __builtin_amdgcn_mfma_f64_16x16x4f64((kv && ii < m) ? x : 0.0, kv ? y : 0.0, V, 0, 0, 0);
+      }
       // chunks of CH tiles: all loads of a chunk are in flight together
       static_for<(NT + CH - 1) / CH>([&](auto ch) __attribute__((always_inline)) {
         constexpr int T0 = decltype(ch)::value * CH;
@@ -209,16 +219,16 @@ struct EngineGW {
             acc[u][decltype(r)::value] = gc[(size_t)r * LT + 16 * u];
           });
         });
-        static_for<TN>([&](auto u) __attribute__((always_inline)) {
-          double rv[K4];
-          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-            const double x = rs[sk[gi] * RSS + 16 * (T0 + u) + ii];
-            rv[gi] = kv[gi] ? x : 0.0;
+        for (int gi = 0; gi < K4; ++gi) {
+          const int k = 4 * gi + qq;
+          const bool kv = k < m;
+          const int sk = (int)(slist >> (4 * k)) & 15;
+          const double a = gi == 0 ? V[0] : gi == 1 ? V[1] : gi == 2 ? V[2] : V[3];
+          static_for<TN>([&](auto u) __attribute__((always_inline)) {
+            const double x = rs[sk * RSS + 16 * (T0 + u) + ii];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, kv ? x : 0.0, acc[u], 0, 0, 0);
           });
-          static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(V[decltype(gi)::value], rv[gi], acc[u], 0, 0, 0);
-          });
-        });
+        }
         static_for<TN>([&](auto u) __attribute__((always_inline)) {
           static_for<4>([&](auto r) __attribute__((always_inline)) {
             gc[(size_t)r * LT + 16 * u] = acc[u][decltype(r)::value];
@@ -231,6 +241,7 @@ struct EngineGW {
   // One window on every wave.  Returns 1 if a ratio of the window's scan was
   // not a positive number (the same on every thread), else 0.
   __device__ __forceinline__ uint32_t window(int ww, int mode, int jf, const uint64_t (&xw)[JW], double* ratio_out) {
+    refresh_ids();
     stage_strips(ww);
     if (wave == 0) scan(ww, mode, jf, xw, ratio_out);
     __syncthreads();
@@ -246,9 +257,7 @@ struct EngineGW {
       });
     }
     if (m) {
-      dispatch<4>((m - 1) >> 2, [&](auto kk) __attribute__((always_inline)) {
-        flush_k<decltype(kk)::value + 1>(ww, m, slist);
-      });
+      flush(ww, m, slist);
       publish();  // the next window stages the updated strips
     }
     return (w1 >> 8) & 1u;
@@ -272,6 +281,7 @@ struct EngineGW {
   // g_s(tau_k) sums S_k = sum_l eps G_s[(l+k) mod L][l], staged through LDS
   // in blocks of rows; thread t = s*L + k returns S_k / L.
   __device__ __forceinline__ double green_sums() {
+    refresh_ids();
     const int sme = tid >= L, k = tid - sme * L;
     double S = 0.0;
     for (int s = 0; s < 2; ++s) {

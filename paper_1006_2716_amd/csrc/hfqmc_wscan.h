@@ -51,6 +51,12 @@ __device__ __forceinline__ void win_rank1(int lane, int c, int j, double fu, dou
                                           double (&bd)[4], double (&qu)[4], double (&qd)[4]) {
   const int src_col = ((lane & 48) | j) << 2;
   const int src_row = (((j & 12) << 2) | c) << 2;
+  // the column first: its permutes do not wait for the row's branch
+  double cu[4], cd[4];
+  static_for<4>([&](auto r) __attribute__((always_inline)) {
+    cu[r] = bperm_d(src_col, bu[r]);
+    cd[r] = bperm_d(src_col, bd[r]);
+  });
   double rbu = 0.0, rbd = 0.0, rqu = 0.0, rqd = 0.0;
   dispatch<4>(j & 3, [&](auto jr) __attribute__((always_inline)) {
     constexpr int R = decltype(jr)::value;
@@ -58,11 +64,6 @@ __device__ __forceinline__ void win_rank1(int lane, int c, int j, double fu, dou
     rbd = bperm_d(src_row, bd[R]);
     rqu = bperm_d(src_row, qu[R]);
     rqd = bperm_d(src_row, qd[R]);
-  });
-  double cu[4], cd[4];
-  static_for<4>([&](auto r) __attribute__((always_inline)) {
-    cu[r] = bperm_d(src_col, bu[r]);
-    cd[r] = bperm_d(src_col, bd[r]);
   });
   const double e = c == j ? 1.0 : 0.0;
   rbu += e;
