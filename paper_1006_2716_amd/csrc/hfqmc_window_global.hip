@@ -54,7 +54,7 @@ struct GWSmem {
 template <class C>
 struct EngineGW {
   static constexpr int LT = C::LT, NT = C::NT, JW = C::JW, CS = C::CS, RSS = C::RSS;
-  static constexpr int CH = (NT + 1) / 2;  // tiles per chunk of the flush: half a tile-row in flight
+  static constexpr int CH = NT;  // tiles per chunk of the flush: a whole tile-row in flight
 
   GWSmem<C>& sm;
   // thread and wave indices; refresh_ids() re-derives them behind an opaque
