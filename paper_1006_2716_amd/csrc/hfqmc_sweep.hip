@@ -435,27 +435,29 @@ struct Engine : SliceState<C::JW> {
   // The tiles are dumped to LDS (both spins at once when they fit) and
   // thread t = s*L + k adds S_k / L of spin s into gacc.
   __device__ __forceinline__ double diag_sum(const double* m, int k) const {
-    // element ((l+k) mod L, l) sits at k*GS + l*(GS+1), minus L*GS once wrapped
+    // element ((l+k) mod L, l) sits at k*GS + l*(GS+1), minus L*GS once
+    // wrapped (l >= L - k).  The same compile-time trip count on every lane,
+    // every load unconditional at a valid address and weighted by +-1 or 0:
+    // per-lane loop bounds and loads under a condition made each load wait
+    // for its own round trip.
     constexpr int S = GS + 1;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const int nw = L - k;  // l < nw: no wrap
-    int l = 0, base = k * GS;
-    for (; l + 4 <= nw; l += 4) {
-      a0 += m[base + l * S];
-      a1 += m[base + (l + 1) * S];
-      a2 += m[base + (l + 2) * S];
-      a3 += m[base + (l + 3) * S];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    // opaque: the addresses are not loop-invariant to the compiler, which
+    // would otherwise keep all of them (and their weights) in registers
+    // across the whole sweep loop
+    __asm__ volatile("" : "+v"(k));
+    const int nw = L - k;
+    const double* p0 = m + k * GS;
+#pragma unroll 2
+    for (int l0 = 0; l0 < LT; l0 += 4) {
+      static_for<4>([&](auto u) __attribute__((always_inline)) {
+        const int l = l0 + u;
+        const bool ok = l < L, wrap = l >= nw;
+        const int at = ok ? (wrap ? l * S - L * GS : l * S) : -k * GS;
+        a[u] += p0[at] * (ok ? (wrap ? -1.0 : 1.0) : 0.0);
+      });
     }
-    for (; l < nw; ++l) a0 += m[base + l * S];
-    base -= L * GS;
-    for (; l + 4 <= L; l += 4) {
-      a1 -= m[base + l * S];
-      a2 -= m[base + (l + 1) * S];
-      a3 -= m[base + (l + 2) * S];
-      a0 -= m[base + (l + 3) * S];
-    }
-    for (; l < L; ++l) a1 -= m[base + l * S];
-    return (a0 + a1) + (a2 + a3);
+    return (a[0] + a[1]) + (a[2] + a[3]);
   }
 
   __device__ __forceinline__ void dump_tiles(double* m) {

@@ -50,9 +50,11 @@ struct WCfg {
   static constexpr int MINB = LT <= 64 ? 2 : 1;
   // registers per lane of a wave (VGPRs + AGPRs) when every wave of
   // MINB workgroups is resident, and the flush form: looped where the
-  // tiles take half of them or more
+  // tiles take half of them or more, or where three or more waves share a
+  // SIMD (the unrolled form spills there, and other waves hide the loop's
+  // latency)
   static constexpr int BUDGET = 512 / ((NW * MINB + 3) / 4);
-  static constexpr bool LOOP = 2 * (RT * NT * 8) >= BUDGET;
+  static constexpr bool LOOP = 2 * (RT * NT * 8) >= BUDGET || BUDGET < 256;
   static_assert(LT % 16 == 0 && NT % RT == 0, "bad tile configuration");
   static_assert(NTH >= LT, "measurement needs one thread per tau_k");
   static_assert(DR * GS <= 4 * 16 * RS, "dump block must fit the row buffers");
@@ -198,6 +200,20 @@ struct EngineW {
     }
   }
 
+  // x where c holds, else 0.  fp64 kernels: as a product, since with a
+  // select the compiler moves the load of x into a branch and every such
+  // load then waits for its own round trip (x is finite: an element of G, P
+  // or the staged strips).  The kernels with fp32 flush products keep the
+  // select: with the product their chains drifted away (deterministically,
+  // at 48 and 64 slices, under either of the two changes that introduced
+  // it); the cause was not found.
+  __device__ __forceinline__ static double keep(bool c, double x) {
+    if constexpr (C::MX)
+      return c ? x : 0.0;
+    else
+      return x * (c ? 1.0 : 0.0);
+  }
+
   // row of the tile fed as V's column ii: permuted for the fp64 accumulator
   // (rows 4*reg + lane/16), natural for fp32 (rows 4*(lane/16) + reg)
   __device__ __forceinline__ static int v_row(int ii, bool f32) { return f32 ? ii : 4 * (ii & 3) + (ii >> 2); }
@@ -235,8 +251,8 @@ struct EngineW {
       static_for<K4>([&](auto gi) __attribute__((always_inline)) {
         const double x = pb[sk[gi] * TS + si];
         const double y = tb[pi * TS + sk[gi]] - ((r == ww && pi == sk[gi]) ? 1.0 : 0.0);
-        av[gi] = (kv[gi] && ii < m) ? x : 0.0;
-        bv[gi] = kv[gi] ? y : 0.0;
+        av[gi] = keep(kv[gi] && ii < m, x);
+        bv[gi] = keep(kv[gi], y);
       });
       wd4 V = {0.0, 0.0, 0.0, 0.0};
       static_for<K4>([&](auto gi) __attribute__((always_inline)) {
@@ -245,8 +261,7 @@ struct EngineW {
       static_for<NT>([&](auto tj) __attribute__((always_inline)) {
         double rv[K4];
         static_for<K4>([&](auto gi) __attribute__((always_inline)) {
-          const double x = rows[sk[gi] * RS + 16 * tj + ii];
-          rv[gi] = kv[gi] ? x : 0.0;
+          rv[gi] = keep(kv[gi], rows[sk[gi] * RS + 16 * tj + ii]);
         });
         static_for<K4>([&](auto gi) __attribute__((always_inline)) {
           tile_update(g[rt][tj], V[decltype(gi)::value], rv[gi], f32);
@@ -268,12 +283,11 @@ struct EngineW {
       const int k = 4 * gi + qq;
       const bool kv = k < m;
       const int sk = (int)(slist >> (4 * k)) & 15;
-      const double x = pb[sk * TS + si];
-      const double av = (kv && ii < m) ? x : 0.0;
+      const double av = keep(kv && ii < m, pb[sk * TS + si]);
       static_for<RT>([&](auto rt) __attribute__((always_inline)) {
         const int r = wr * RT + rt;
         const double y = sm.tb[wave][rt][pi * TS + sk] - ((r == ww && pi == sk) ? 1.0 : 0.0);
-        V[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, kv ? y : 0.0, V[rt], 0, 0, 0);
+        V[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, keep(kv, y), V[rt], 0, 0, 0);
       });
     }
     for (int gi = 0; gi < K4; ++gi) {
@@ -285,8 +299,7 @@ struct EngineW {
         a[rt] = gi == 0 ? V[rt][0] : gi == 1 ? V[rt][1] : gi == 2 ? V[rt][2] : V[rt][3];
       });
       static_for<NT>([&](auto tj) __attribute__((always_inline)) {
-        const double x = rows[sk * RS + 16 * tj + ii];
-        const double rv = kv ? x : 0.0;
+        const double rv = keep(kv, rows[sk * RS + 16 * tj + ii]);
         static_for<RT>([&](auto rt) __attribute__((always_inline)) { tile_update(g[rt][tj], a[rt], rv, f32); });
       });
     }
@@ -330,9 +343,17 @@ struct EngineW {
     for (int t0 = 0; t0 < n; t0 += 8) {
       static_for<8>([&](auto u) __attribute__((always_inline)) {
         const int i = i0 + t0 + u;
-        const bool wrap = i < k;
-        const double x = m[(i - r0) * GS + (wrap ? i - k + L : i - k)];
-        a[u] += (t0 + u < n && i < L) ? (wrap ? -x : x) : 0.0;
+        const bool ok = t0 + u < n && i < L, wrap = i < k;
+        if constexpr (C::MX) {  // the select form (see keep())
+          const double x = m[(i - r0) * GS + (wrap ? i - k + L : i - k)];
+          a[u] += ok ? (wrap ? -x : x) : 0.0;
+        } else {
+          // every load at a valid address and unconditional, the element
+          // weighted by +-1 or 0: a load feeding a select is moved into a
+          // branch, and each then waits for its own round trip
+          const int at = ok ? (i - r0) * GS + (wrap ? i - k + L : i - k) : 0;
+          a[u] += m[at] * (ok ? (wrap ? -1.0 : 1.0) : 0.0);
+        }
       });
     }
     return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));

@@ -98,6 +98,11 @@ struct EngineGW {
 
   __device__ __forceinline__ gdouble* gs(int s) const { return gm + (size_t)s * LT * LT; }
 
+  // x where c holds, else 0, as a product: with a select the compiler moves
+  // the load of x into a branch that waits for its own round trip (x is
+  // finite: an element of P or of the staged strips)
+  __device__ __forceinline__ static double keep(bool c, double x) { return x * (c ? 1.0 : 0.0); }
+
   // G = G0 of both spins: the antiperiodic matrix of the Weiss samples.
   __device__ __forceinline__ void set_weiss() {
     for (int idx = tid; idx < 2 * LT * LT; idx += C::NTH) {
@@ -205,7 +210,7 @@ struct EngineGW {
         const int sk = (int)(slist >> (4 * k)) & 15;
         const double x = pb[sk * CS + si];
         const double y = cs[(16 * ti + pi) * CS + sk] - ((ti == ww && pi == sk) ? 1.0 : 0.0);
-        V = __builtin_amdgcn_mfma_f64_16x16x4f64((kv && ii < m) ? x : 0.0, kv ? y : 0.0, V, 0, 0, 0);
+        V = __builtin_amdgcn_mfma_f64_16x16x4f64(keep(kv && ii < m, x), keep(kv, y), V, 0, 0, 0);
       }
       // chunks of CH tiles: all loads of a chunk are in flight together
       static_for<(NT + CH - 1) / CH>([&](auto ch) __attribute__((always_inline)) {
@@ -226,7 +231,7 @@ struct EngineGW {
           const double a = gi == 0 ? V[0] : gi == 1 ? V[1] : gi == 2 ? V[2] : V[3];
           static_for<TN>([&](auto u) __attribute__((always_inline)) {
             const double x = rs[sk * RSS + 16 * (T0 + u) + ii];
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, kv ? x : 0.0, acc[u], 0, 0, 0);
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, keep(kv, x), acc[u], 0, 0, 0);
           });
         }
         static_for<TN>([&](auto u) __attribute__((always_inline)) {
