@@ -63,7 +63,7 @@ RECOMPUTE_EVERY = 50
 PROFILED_TRAFFIC = {
     # kernel: (source files, sha256 prefix, bytes per launch)
     "hfqmc::sweep_kernel<Cfg<64,2,0>>": (("hfqmc_sweep.hip", "hfqmc_device.h", "hfqmc_internal.h"),
-                                         "4d4c17e81d65ff43", 2.533e7),
+                                         "17d1141ae7a6dc7b", 2.5545e7),
 }
 
 
