@@ -204,9 +204,9 @@ struct EngineW {
   // select the compiler moves the load of x into a branch and every such
   // load then waits for its own round trip (x is finite: an element of G, P
   // or the staged strips).  The kernels with fp32 flush products keep the
-  // select: with the product their chains drifted away (deterministically,
-  // at 48 and 64 slices, under either of the two changes that introduced
-  // it); the cause was not found.
+  // select form, here and in the g(tau) sums: built with the product form,
+  // their chains' drift grew without bound at 48 and 64 slices (the same
+  // result on every run), for a reason not found.
   __device__ __forceinline__ static double keep(bool c, double x) {
     if constexpr (C::MX)
       return c ? x : 0.0;
