@@ -1044,13 +1044,17 @@ hfqmc_status srv_finish(hfqmc_ctx* c, Request* r) {
 }
 
 // Time per proposal of one chain of a kernel class, as measured on MI355X
-// with about one impurity per CU: ~0.75 us for the register-tile kernels up
-// to L = 64, growing about linearly in L beyond, ~3 us at L = 160 for the
-// device-memory kernel.  Used to give every class about `step_ms` of work
-// per step.
+// with one or two impurities per CU (512-impurity classes of the chain
+// workload, 2200 sweeps): 0.4 us at 32 slices, 0.55 us at 48-64 (rank-one
+// kernels), 0.85 us at 80, 0.5 - 0.6 us at 96-128 (window kernels), 1.35 us
+// at L = 160 on the device-memory kernel.  Used to give every class about
+// `step_ms` of work per step.
 double model_us_per_proposal(const hfqmc_site* s) {
-  if (s->RT == 0) return 3.0 * s->L / 160.0;
-  return 0.75 * (s->L > 64 ? s->L / 64.0 : 1.0);
+  if (s->RT == 0) return 1.35 * s->L / 160.0;
+  if (s->LT <= 32) return 0.4;
+  if (s->LT <= 64) return 0.55;
+  if (s->LT <= 80) return 0.85;
+  return 0.6;
 }
 
 // One pass of the engine.  Work advances in lockstep steps: a step launches
