@@ -494,6 +494,8 @@ def main():
     ap.add_argument("--delay", type=int, default=0,
                     help="update kind: 0 the library's choice for L (default), 1 rank-one, 2..32 delayed rank-k")
     ap.add_argument("--no-serving", action="store_true", help="headline: skip the serving-latency leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="headline: skip the uneven-L, L = 160 and slab legs (each run in a process of its own)")
     ap.add_argument("--tune-cache", default=None, help="serving: a tuning cache fixing kernel shapes per padded L")
     ap.add_argument("--shape", default=None, metavar="RT,K",
                     help="headline: force the L = 64 kernel shape (tile-rows per wave, k: 0 window, 1 rank-one, "
@@ -668,6 +670,31 @@ def main():
             out["serving"]["workload"] = srv["config"]["workload"]
         else:
             out["serving"] = {"error": f"serving leg exited {cp.returncode}"}
+    if not args.no_workloads:
+        # the other benchmark configurations, each in a process of its own:
+        # their headline figures ride on this line
+        import subprocess
+        out["workloads"] = {}
+        for n in ("uneven", "long", "slab"):
+            cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", n], capture_output=True,
+                                text=True)
+            line = [x for x in cp.stdout.splitlines() if x.startswith("{")]
+            if cp.returncode != 0 or not line:
+                out["workloads"][n] = {"error": f"{n} leg exited {cp.returncode}"}
+                continue
+            w = json.loads(line[-1])
+            e = {k: w[k] for k in ("metric", "value", "unit", "ms_per_step") if k in w}
+            e["workload"] = w["config"]["workload"]
+            if n == "uneven":
+                e["class_launch_ms_L_items"] = w["config"].get("class_launch_ms_L_items")
+                mx = w.get("mixed_fp32_products", {}).get("window", {})
+                e["mixed_window"] = {k: mx.get(k) for k in ("proposals_per_s", "failed", "max_drift")}
+            elif n == "long":
+                e["us_per_proposal_of_a_chain"] = w.get("legs", {}).get("window", {}).get("us_per_proposal_of_a_chain")
+            elif n == "slab":
+                mx = w.get("legs", {}).get("mixed", {})
+                e["mixed"] = {k: mx.get(k) for k in ("proposals_per_s", "failed", "max_drift")}
+            out["workloads"][n] = e
     print(json.dumps(out))
 
 
