@@ -1549,17 +1549,23 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
   classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
   const int dk_delayed = c->prec == HFQMC_MIXED ? 2 : 1;
   for (int LT : classes) {
-    // the class's problems with shortened chains (same Weiss, U, beta, seeds)
-    std::vector<hfqmc_problem> sample;
+    // the class's problems with shortened chains (same Weiss, U, beta,
+    // seeds), at two lengths: the rate is taken from the difference, so the
+    // per-launch costs that a full-length run amortises (the first Dyson
+    // solve, the launch itself) do not decide between shapes
+    std::vector<hfqmc_problem> sample, sample2;
     int64_t props = 0;
     for (int i = 0; i < n; ++i)
       if (padded_L(p[i].L) == LT) {
         hfqmc_problem q = p[i];
         q.n_warmup = sweeps / 2;
         q.n_measure = (int64_t)(sweeps - sweeps / 2) * chains_of(q);
-        q.n_bins = 2;
+        q.n_bins = std::min(q.n_bins, 2);
         sample.push_back(q);
-        props += (int64_t)sweeps * q.L * chains_of(q);
+        q.n_warmup = sweeps;
+        q.n_measure = (int64_t)sweeps * chains_of(q);
+        sample2.push_back(q);
+        props += (int64_t)sweeps * q.L * chains_of(q);  // the difference of the two lengths
       }
     std::vector<Plan> cands;
     int rts[16];
@@ -1590,17 +1596,25 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
     TuneEntry dflt = best;
     std::string measured;
     for (const Plan& pl : cands) {
-      TRY(stage_impl(c, sample.data(), (int)sample.size(), d_ws, ws_bytes, &pl));
-      double ms = 1e300;
-      for (int rep = 0; rep < 2; ++rep) {
-        HIP_TRY(hipEventRecord(c->ev_start, c->stream));
-        TRY(enqueue_pass(c, c->stream, false));
-        HIP_TRY(hipEventRecord(c->ev_end, c->stream));
-        double t = 0;
-        TRY(pass_ms(c, &t));
-        if (rep > 0) ms = std::min(ms, t);
+      double tl[2];
+      for (int len = 0; len < 2; ++len) {
+        const std::vector<hfqmc_problem>& sm = len ? sample2 : sample;
+        TRY(stage_impl(c, sm.data(), (int)sm.size(), d_ws, ws_bytes, &pl));
+        double ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(hipEventRecord(c->ev_start, c->stream));
+          TRY(enqueue_pass(c, c->stream, false));
+          HIP_TRY(hipEventRecord(c->ev_end, c->stream));
+          double t = 0;
+          TRY(pass_ms(c, &t));
+          if (rep > 0) ms = std::min(ms, t);
+        }
+        tl[len] = ms;
       }
-      const double rate = (double)props / (ms * 1e-3);
+      // twice the sweeps minus once: the time of `sweeps` sweeps without the
+      // fixed costs (the longer run alone if noise made the difference small)
+      const double dt = tl[1] - tl[0] > 0.25 * tl[1] ? tl[1] - tl[0] : 0.5 * tl[1];
+      const double rate = (double)props / (dt * 1e-3);
       char buf[96];
       std::snprintf(buf, sizeof buf, "%s[%d, %d, %.6g]", measured.empty() ? "" : ", ", pl.rt, pl.k, rate);
       measured += buf;
