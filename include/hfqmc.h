@@ -97,9 +97,12 @@ typedef struct {
                                    2..32: delayed rank-k updates, flushed into G
                                    every k accepted flips (fp32 products when
                                    the context precision is HFQMC_MIXED).
-                                   L > 128 always runs delayed fp64 updates with
-                                   G in device memory: delay 0 means 16, 1..16
-                                   the depth, more is EINVAL */
+                                   L > 128 keeps G in device memory, fp64 in
+                                   either precision: delay 0 runs window
+                                   updates where that kernel is compiled
+                                   (padded L 144 and 160), else delayed updates
+                                   of depth 16; 1..16 delayed updates of that
+                                   depth; more is EINVAL */
     int32_t n_chains;           /* independent Markov chains for this impurity
                                    (0 or 1: one).  Chain j draws with Philox
                                    counter word 3 = j, runs the full warm-up and
