@@ -67,8 +67,10 @@ typedef enum {
     HFQMC_ENOTFOUND = -6
 } hfqmc_status;
 
-/* FP64: everything in fp64.  MIXED: delayed-update products in fp32 with fp64
- * accumulation into G; ratios and the Dyson recompute stay fp64. */
+/* FP64: everything in fp64.  MIXED: the rank-k products of the window or
+ * delayed updates in fp32, added into the fp64 G; ratios, the decisions of a
+ * window and the Dyson recompute stay fp64.  Classes with no fp32-product
+ * kernel (the window kernel at 128 slices, G in device memory) run fp64. */
 typedef enum { HFQMC_FP64 = 0, HFQMC_MIXED = 1 } hfqmc_precision;
 
 typedef struct hfqmc_ctx hfqmc_ctx;   /* opaque; one per device and stream */
