@@ -31,6 +31,12 @@
  *     sweeps (after n_warmup) contribute g_sigma(tau_k) (k = 0..L, with
  *     g(tau_L) = n_sigma), n_sigma and d = <n_up n_dn> to n_bins consecutive
  *     bins (measured sweep m goes to bin floor(m n_bins / n_measure)).
+ *   - Checkpoints: a chain's whole state between sweeps is its fields and
+ *     its sweep count w.  A run given init_fields = the final fields of a
+ *     run of w sweeps and sweep_offset = w continues that chain with the same
+ *     random numbers; when w is a multiple of recompute_every (and no drift
+ *     over the limit shortened the interval) both rebuild G from scratch at
+ *     sweep w and the continuation is bit-exact.
  *
  * Memory ownership.  The caller owns every host buffer and ALL device memory:
  * the workspace of hfqmc_solve and the pool of the site/serving calls are

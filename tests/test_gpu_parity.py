@@ -113,6 +113,27 @@ def test_given_initial_fields_and_sweep_offset(ctx):
     _compare_runs(gpu, ref, [p])
 
 
+@pytest.mark.parametrize("L", [64, 96, 160])
+def test_resume_from_saved_fields_is_bit_exact(ctx, L):
+    # a chain saved after 10 sweeps (its fields) and resumed with
+    # sweep_offset = 10 continues bit for bit, since both runs rebuild G from
+    # scratch there (recompute_every = 10 puts a scheduled solve at that sweep)
+    print(f"resume L={L}", flush=True)
+    base = _chain_problem(L, U=6.0, mu=0.2, beta=0.25 * L, seed=5, site=L, n_measure=20, n_bins=4)
+    base["recompute_every"] = 10
+    whole = ctx.solve([dict(base, n_warmup=17)])[0]
+    first = ctx.solve([dict(base, n_warmup=4, n_measure=6, n_bins=2)])[0]
+    resumed = dict(base, n_warmup=7, init_fields=first["fields"].copy(), sweep_offset=10)
+    rest = ctx.solve([resumed])[0]
+    assert np.array_equal(whole["fields"], rest["fields"])
+    assert np.array_equal(whole["bins"], rest["bins"])  # bitwise
+    for k in ("n_up", "n_dn", "docc"):
+        assert whole[k] == rest[k], k
+    for k in ("accepts", "proposals"):  # warm-up included: the two legs add up
+        assert whole[k] == first[k] + rest[k], k
+    _compare_runs([rest], oracle.run([resumed]), [resumed])
+
+
 def test_batch_composition_does_not_change_results(ctx):
     print("composition", flush=True)
     probs = [_chain_problem(L, U=6.0, mu=0.2, beta=5.0, seed=9, site=i, n_warmup=5, n_measure=40)
