@@ -158,7 +158,9 @@ hfqmc_status hfqmc_workspace_size(hfqmc_ctx *ctx, const hfqmc_problem *problems,
 
 /* Solve n independent impurity problems in one batch (blocking).
  * d_ws: caller-owned device memory of ws_bytes >= hfqmc_workspace_size.
- * out: n caller-owned results.  Equivalent to stage + run + collect. */
+ * out: n caller-owned results.  Equivalent to stage + run + collect.  n = 0
+ * is an empty batch: HFQMC_OK, nothing run (problems, d_ws, out may be NULL);
+ * n < 0 is HFQMC_EINVAL. */
 hfqmc_status hfqmc_solve(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes,
                          hfqmc_result *out);
 
@@ -200,8 +202,8 @@ hfqmc_status hfqmc_debug_poison(hfqmc_ctx *ctx, int64_t sweep_a, int64_t sweep_b
  * about 390 impurities fit).  Every call on a device uses the same array, so
  * calls that overlap on one device (from several contexts or threads) race;
  * a call leaves the array holding its batch, and the next call restages
- * every input and clears every accumulator it reads.  Results as
- * hfqmc_solve. */
+ * every input and clears every accumulator it reads.  Results, and the
+ * empty batch, as hfqmc_solve. */
 hfqmc_status hfqmc_solve_static(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, hfqmc_result *out);
 
 /* Split form of hfqmc_solve.  stage: validate, plan, copy inputs to d_ws
@@ -210,7 +212,7 @@ hfqmc_status hfqmc_solve_static(hfqmc_ctx *ctx, const hfqmc_problem *problems, i
  * called repeatedly -- every call recomputes the same deterministic result
  * from the staged inputs.  collect: wait, copy bins/status back, finalise
  * results (bin means and errors).  The staged d_ws must stay valid between
- * the three calls. */
+ * the three calls.  stage needs n >= 1 (HFQMC_EINVAL otherwise). */
 hfqmc_status hfqmc_stage(hfqmc_ctx *ctx, const hfqmc_problem *problems, int32_t n, void *d_ws, size_t ws_bytes);
 hfqmc_status hfqmc_run(hfqmc_ctx *ctx);
 hfqmc_status hfqmc_collect(hfqmc_ctx *ctx, hfqmc_result *out);

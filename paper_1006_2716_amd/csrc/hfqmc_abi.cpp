@@ -1423,6 +1423,7 @@ hfqmc_status hfqmc_debug_poison(hfqmc_ctx* c, int64_t sweep_a, int64_t sweep_b) 
 }
 
 hfqmc_status hfqmc_solve_static(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, hfqmc_result* out) {
+  if (c && n == 0) return HFQMC_OK;  // an empty batch: nothing to run
   if (!c || !p || n < 1 || !out) return fail(HFQMC_EINVAL, "hfqmc_solve_static: bad arguments");
   size_t need = 0;
   TRY(hfqmc_workspace_size(c, p, n, &need));
@@ -1530,6 +1531,7 @@ hfqmc_status hfqmc_collect(hfqmc_ctx* c, hfqmc_result* out) {
 
 hfqmc_status hfqmc_solve(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d_ws, size_t ws_bytes,
                          hfqmc_result* out) {
+  if (c && n == 0) return HFQMC_OK;  // an empty batch: nothing to run
   if (!out) return fail(HFQMC_EINVAL, "hfqmc_solve: out is NULL");
   TRY(hfqmc_stage(c, p, n, d_ws, ws_bytes));
   TRY(hfqmc_run(c));

@@ -318,6 +318,9 @@ class Context:
         return torch.empty(self.workspace_size(problems), dtype=torch.uint8, device=f"cuda:{self.device}")
 
     def solve(self, problems, workspace=None):
+        if len(problems) == 0:  # the library's empty batch: nothing runs
+            _check(lib().hfqmc_solve(self.h, None, 0, None, 0, None), "hfqmc_solve")
+            return []
         self.stage(problems, workspace)
         self.run()
         return self.collect()

@@ -207,6 +207,19 @@ def test_full_size_L64_batch_sampled(ctx):
     assert all(g["status"] == 0 for g in gpu)
 
 
+def test_empty_batch(ctx):
+    from paper_1006_2716_amd import hfqmc
+    print("empty batch", flush=True)
+    assert ctx.solve([]) == []
+    assert ctx.solve_static([]) == []
+    L = hfqmc.lib()
+    assert L.hfqmc_solve(ctx.h, None, -1, None, 0, None) == hfqmc.EINVAL
+    assert L.hfqmc_stage(ctx.h, None, 0, None, 0) == hfqmc.EINVAL  # nothing to stage
+    # the context is untouched: a batch after the empty ones runs as usual
+    p = _chain_problem(20, U=4.0, mu=0.1, beta=5.0, n_warmup=3, n_measure=12)
+    _compare_runs(ctx.solve([p]), oracle.run([p]), [p])
+
+
 def test_invalid_problems_raise(ctx):
     from paper_1006_2716_amd import hfqmc
     p = _chain_problem(16, U=4.0, mu=0.0, beta=4.0)
