@@ -241,8 +241,10 @@ hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx *ctx, int32_t i, double *ms, int32_t
  * matrix-core update of G), rank-one, or delayed with k in {4, 8, 16, 32};
  * fp32 products in the context precision HFQMC_MIXED) on those problems
  * shortened to `sweeps` (>= 4) and to 2 `sweeps` sweeps, the rate taken
- * from the difference of the two times (so per-launch costs do not count),
- * keep the fastest unless the class's untuned default comes within 5 % of
+ * from the difference of the two times (so per-launch costs do not count);
+ * every timing run holds the whole shortened batch, the other classes in
+ * their current shapes, so a shape is timed beside the classes it shares
+ * the GPU with.  Keep the fastest unless the class's untuned default comes within 5 % of
  * it, and write the table to the context's tune cache (JSON,
  * if a path was given to hfqmc_create).  Problems with delay 0 then use the
  * tuned shape.  d_ws must hold hfqmc_workspace_size(problems); any staged

@@ -343,6 +343,7 @@ struct Group {
   int LT, rt, dk;
   int first, count, grid;
   int stream = 0;  // index into the pass's streams (0: the context stream)
+  bool tuned = false;  // the class an autotuning run times
 };
 
 // A batch with every problem split into its chains: item k runs chain
@@ -766,11 +767,13 @@ Plan plan_for(const hfqmc_ctx* c, const hfqmc_problem& p) {
 
 // Stage a batch: group by kernel class (padded L, shape), order items inside
 // a class by descending work, upload descriptors and inputs.  `force`, when
-// set, overrides the plan of every problem (autotuning).  `streams`: create
-// the auxiliary streams the pass forks onto (not for the static entry point,
-// which creates nothing and runs the classes in turn on the context stream).
+// set, overrides the plan of every problem, or with force_LT of the problems
+// of that padded L only, which then launch apart from the rest (autotuning:
+// the class is timed beside the others).  `streams`: create the auxiliary
+// streams the pass forks onto (not for the static entry point, which creates
+// nothing and runs the classes in turn on the context stream).
 hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_ws, size_t ws_bytes,
-                        const Plan* force, bool streams = true) {
+                        const Plan* force, bool streams = true, int force_LT = 0) {
   for (int i = 0; i < n0; ++i) TRY(validate(p0[i], i));
   const Expanded ex = expand(p0, n0);  // from here on a work item is one chain
   const hfqmc_problem* p = ex.items.data();
@@ -787,10 +790,12 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
 
   std::vector<int> idx(n);
   std::vector<Plan> plan(n);
+  std::vector<char> forced(n, 0);
   for (int i = 0; i < n; ++i) {
     idx[i] = i;
-    plan[i] = force ? *force : plan_for(c, p[i]);
-    if (force) plan[i].LT = kernel_LT(p[i].L, plan[i].dk);
+    forced[i] = force && (force_LT == 0 || padded_L(p[i].L) == force_LT);
+    plan[i] = forced[i] ? *force : plan_for(c, p[i]);
+    if (forced[i]) plan[i].LT = kernel_LT(p[i].L, plan[i].dk);
     if (plan[i].rt == 0 && plan[i].k > kGlobalMaxDelay)
       return fail(HFQMC_EINVAL, "problem %d: delay %d > %d for L=%d", ex.owner[i], plan[i].k, kGlobalMaxDelay, p[i].L);
     if (!find_kernel(plan[i].LT, plan[i].rt, plan[i].dk))
@@ -807,7 +812,8 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
     const double lam = coupling(p[i].beta / p[i].L, p[i].U);
     return (double)(p[i].n_warmup + p[i].n_measure) * p[i].L * std::max(p[i].L, 64) * std::exp(-0.76 * lam * lam);
   };
-  auto key = [&](int i) { return std::make_tuple(-plan[i].LT, plan[i].dk, plan[i].rt); };
+  // the class an autotuning run times keeps launches of its own
+  auto key = [&](int i) { return std::make_tuple(-plan[i].LT, plan[i].dk, plan[i].rt, force_LT && forced[i]); };
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
     if (key(a) != key(b)) return key(a) < key(b);
     return cost(a) > cost(b);
@@ -823,6 +829,7 @@ hfqmc_status stage_impl(hfqmc_ctx* c, const hfqmc_problem* p0, int n0, void* d_w
     HIP_TRY(kernel_occupancy(ki, &bpc));
     if (bpc < 1) return fail(HFQMC_EDEVICE, "kernel for L=%d does not fit on a CU", LT);
     groups.push_back({ki, LT, pl.rt, pl.dk, k, e - k, std::min(e - k, bpc * c->n_cu)});
+    groups.back().tuned = force_LT && forced[idx[k]];
     k = e;
   }
   if (groups.size() > 64) return fail(HFQMC_EINVAL, "too many kernel classes");
@@ -1550,24 +1557,31 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
   std::sort(classes.begin(), classes.end());
   classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
   const int dk_delayed = c->prec == HFQMC_MIXED ? 2 : 1;
+  // the whole batch with shortened chains (same Weiss, U, beta, seeds), at
+  // two lengths: a class's rate is taken from the difference, so the
+  // per-launch costs that a full-length run amortises (the first Dyson
+  // solve, the launch itself) do not decide between shapes.  Every class
+  // runs in each timing run, as in a pass, so a shape is timed beside the
+  // classes it will share the CUs with (alone, with one impurity per CU, a
+  // shape with more waves can win and then lose beside the others)
+  std::vector<hfqmc_problem> sample, sample2;
+  for (int i = 0; i < n; ++i) {
+    hfqmc_problem q = p[i];
+    q.n_warmup = sweeps / 2;
+    q.n_measure = (int64_t)(sweeps - sweeps / 2) * chains_of(q);
+    q.n_bins = std::min(q.n_bins, 2);
+    sample.push_back(q);
+    q.n_warmup = sweeps;
+    q.n_measure = (int64_t)sweeps * chains_of(q);
+    sample2.push_back(q);
+  }
   for (int LT : classes) {
-    // the class's problems with shortened chains (same Weiss, U, beta,
-    // seeds), at two lengths: the rate is taken from the difference, so the
-    // per-launch costs that a full-length run amortises (the first Dyson
-    // solve, the launch itself) do not decide between shapes
-    std::vector<hfqmc_problem> sample, sample2;
-    int64_t props = 0;
+    int64_t props = 0;  // the difference of the two lengths
+    int first = -1;
     for (int i = 0; i < n; ++i)
       if (padded_L(p[i].L) == LT) {
-        hfqmc_problem q = p[i];
-        q.n_warmup = sweeps / 2;
-        q.n_measure = (int64_t)(sweeps - sweeps / 2) * chains_of(q);
-        q.n_bins = std::min(q.n_bins, 2);
-        sample.push_back(q);
-        q.n_warmup = sweeps;
-        q.n_measure = (int64_t)sweeps * chains_of(q);
-        sample2.push_back(q);
-        props += (int64_t)sweeps * q.L * chains_of(q);  // the difference of the two lengths
+        props += (int64_t)sweeps * p[i].L * chains_of(p[i]);
+        if (first < 0) first = i;
       }
     std::vector<Plan> cands;
     int rts[16];
@@ -1589,7 +1603,7 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
     // the untuned default of the class, timed like the others (added when
     // it is not a candidate: the fp64 window kernel serving a mixed context)
     c->tune.erase(LT);
-    hfqmc_problem q0 = sample[0];
+    hfqmc_problem q0 = sample[first];
     q0.delay = 0;
     const Plan def = plan_for(c, q0);
     auto same = [](const Plan& a, const Plan& b) { return a.rt == b.rt && a.dk == b.dk && a.k == b.k; };
@@ -1601,14 +1615,18 @@ hfqmc_status hfqmc_tune(hfqmc_ctx* c, const hfqmc_problem* p, int32_t n, void* d
       double tl[2];
       for (int len = 0; len < 2; ++len) {
         const std::vector<hfqmc_problem>& sm = len ? sample2 : sample;
-        TRY(stage_impl(c, sm.data(), (int)sm.size(), d_ws, ws_bytes, &pl));
+        TRY(stage_impl(c, sm.data(), (int)sm.size(), d_ws, ws_bytes, &pl, true, LT));
         double ms = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
-          HIP_TRY(hipEventRecord(c->ev_start, c->stream));
-          TRY(enqueue_pass(c, c->stream, false));
-          HIP_TRY(hipEventRecord(c->ev_end, c->stream));
-          double t = 0;
-          TRY(pass_ms(c, &t));
+          TRY(enqueue_pass(c, c->stream, true));
+          HIP_TRY(hipStreamSynchronize(c->stream));
+          double t = 0;  // the class's own launch (its stream's events)
+          for (size_t gi = 0; gi < c->groups.size(); ++gi)
+            if (c->groups[gi].tuned) {
+              float e = 0.f;
+              HIP_TRY(hipEventElapsedTime(&e, c->ev[2 * gi], c->ev[2 * gi + 1]));
+              t = std::max(t, (double)e);
+            }
           if (rep > 0) ms = std::min(ms, t);
         }
         tl[len] = ms;
