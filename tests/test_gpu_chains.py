@@ -72,6 +72,17 @@ def test_pooled_chains_match_oracle(ctx):
         _check_pooled(g, p)
 
 
+def test_largest_chain_count(ctx):
+    """64 chains (the most a problem may have; 191 measured sweeps: 63 chains
+    run 3, the last 2), on a register and a device-memory kernel."""
+    probs = [_problem(L, U=5.0, mu=0.05, n_chains=64, site=30 + L, n_warmup=3, n_measure=64 * 2 + 63, n_bins=2)
+             for L in (16, 144)]
+    print("64 chains", [p["L"] for p in probs], flush=True)
+    gpu = ctx.solve(probs)
+    for g, p in zip(gpu, probs):
+        _check_pooled(g, p)
+
+
 def test_one_chain_is_the_plain_run(ctx):
     p = _problem(48, U=6.0, mu=0.1, n_chains=0)
     a = ctx.solve([p])[0]
