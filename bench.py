@@ -455,8 +455,8 @@ def bench_thermo(args):
     sites = np.arange(n * n, dtype=np.int32)
     ctx = hfqmc.Context(0)
     t0 = time.perf_counter()
-    r = entropy_scan(ctx, hop, n, eps, eps_seed, U, mus, 38, 42, dtau, sites, 100, 2000, seed=5, n_freq=500,
-                     tol=5e-3, max_iter=5, n_bins=16, mu_group=args.mu_group)
+    r = entropy_scan(ctx, hop, n, eps, eps_seed, U, mus, 38, 42, dtau, sites, 100, args.thermo_sweeps, seed=5,
+                     n_freq=500, tol=5e-3, max_iter=args.thermo_iters, n_bins=16, mu_group=args.mu_group)
     ms = (time.perf_counter() - t0) * 1e3
     ctx.close()
     c = n * n // 2
@@ -466,8 +466,9 @@ def bench_thermo(args):
     _line("entropy scan, 13x13 trap (45 mu x 2 T, converged RDMFT): proposals/s", r["proposals"] / (ms * 1e-3),
           "proposals/s", 1, 0, ms,
           {"workload": "13x13 open trap V0=0.25, U=10, dtau=0.1, L=38/42, mu-U/2 from -11 to 0 (45 points), "
-                       "staggered seed 0.1 in the first iteration at each point, 100+2000 sweeps, <=5 iterations "
-                       "per point, " + f"{args.mu_group} chemical potential(s) per solver batch",
+                       "staggered seed 0.1 in the first iteration at each point, "
+                       f"100+{args.thermo_sweeps} sweeps, <={args.thermo_iters} iterations per point, "
+                       f"{args.mu_group} chemical potential(s) per solver batch",
            "proposals": r["proposals"], "rdmft_iterations": int(sum(r["iterations"]))},
           T=r["T"], atoms=N, entropy_central=float(r["s"][-1][c]), entropy_central_err=float(r["s_err"][-1][c]),
           entropy_per_particle=float(r["s"][-1].sum() / N),
@@ -505,6 +506,8 @@ def main():
     ap.add_argument("--step-ms", type=float, default=8.0, help="serving: target step duration")
     ap.add_argument("--quantum", type=int, default=0, help="serving: fixed proposals per request per step")
     ap.add_argument("--serve-chains", type=int, default=1, help="serving: chains per L = 160 request")
+    ap.add_argument("--thermo-sweeps", type=int, default=2000, help="thermo: measured sweeps per solve")
+    ap.add_argument("--thermo-iters", type=int, default=5, help="thermo: most RDMFT iterations per (mu, T) point")
     ap.add_argument("--mu-group", type=int, default=9,
                     help="thermo: chemical potentials whose loops share one solver batch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
