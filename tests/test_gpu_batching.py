@@ -138,6 +138,35 @@ def test_autotuner_picks_measured_shape_and_persists(tmp_path):
         torch.cuda.synchronize()
 
 
+def test_autotuner_classes_sharing_a_kernel(tmp_path):
+    # 112 slices run on the 128-slice window kernels: while the 112-slice
+    # class is timed with a window shape, its launch stays apart from the
+    # 128-slice class's even where both use the same kernel
+    import torch
+    from paper_1006_2716_amd import hfqmc
+    probs = wl.chain_batch(n_imp=16, Ls=(112, 128), n_warmup=3, n_measure=8, seed=21)
+    for p in probs:
+        p["n_bins"] = 2
+    c = hfqmc.Context(0, tune_cache=str(tmp_path / "tune.json"))
+    try:
+        print("tuning 112 + 128", flush=True)
+        c.tune(probs, sweeps=8)
+        ents = {e["L_padded"]: e for e in json.loads((tmp_path / "tune.json").read_text())["entries"]}
+        assert set(ents) == {112, 128}
+        for e in ents.values():
+            rates = [m[2] for m in e["measured"]]
+            assert all(r > 0 for r in rates) and e["proposals_per_s"] * 1.05 >= max(rates)
+        sub = [next(p for p in probs if p["L"] == L) for L in (112, 128)]
+        got = c.solve(sub)
+        ref = oracle.run(sub, n_threads=2)
+        for p, g, r in zip(sub, got, ref):
+            assert np.array_equal(g["fields"], r["fields"]), p["L"]
+            assert np.max(np.abs(g["bins"] - r["bins"])) < 1e-8
+    finally:
+        c.close()
+        torch.cuda.synchronize()
+
+
 def test_tune_cache_ignores_foreign_or_broken_entries(tmp_path):
     """A cache for another architecture, a malformed file, or entries naming
     shapes this build does not have leave the untuned defaults in place."""
