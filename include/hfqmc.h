@@ -33,8 +33,8 @@
  *     bins (measured sweep m goes to bin floor(m n_bins / n_measure)).
  *   - Checkpoints: a chain's whole state between sweeps is its fields and
  *     its sweep count w.  A run given init_fields = the final fields of a
- *     run of w sweeps and sweep_offset = w continues that chain with the same
- *     random numbers; when w is a multiple of recompute_every (and no drift
+ *     run of w sweeps and sweep_offset = w (plus that run's own offset)
+ *     continues that chain with the same random numbers; when w is a multiple of recompute_every (and no drift
  *     over the limit shortened the interval) both rebuild G from scratch at
  *     sweep w and the continuation is bit-exact.
  *
@@ -244,8 +244,8 @@ hfqmc_status hfqmc_last_launch_ms(hfqmc_ctx *ctx, int32_t i, double *ms, int32_t
  * from the difference of the two times (so per-launch costs do not count);
  * every timing run holds the whole shortened batch, the other classes in
  * their current shapes, so a shape is timed beside the classes it shares
- * the GPU with.  Keep the fastest unless the class's untuned default comes within 5 % of
- * it, and write the table to the context's tune cache (JSON,
+ * the GPU with.  Keep the fastest unless the class's untuned default comes
+ * within 5 % of it, and write the table to the context's tune cache (JSON,
  * if a path was given to hfqmc_create).  Problems with delay 0 then use the
  * tuned shape.  d_ws must hold hfqmc_workspace_size(problems); any staged
  * batch is discarded (stage again). */
