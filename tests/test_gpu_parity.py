@@ -207,6 +207,34 @@ def test_full_size_L64_batch_sampled(ctx):
     assert all(g["status"] == 0 for g in gpu)
 
 
+def test_full_size_uneven_batch_sampled(ctx):
+    """512 impurities with L drawn from {32, 48, 64, 96, 128}, 200 + 2000
+    sweeps, in the uneven-L benchmark's launch configuration (every class
+    on its default kernel, classes concurrent); the heaviest impurity of
+    each class is recomputed by the oracle."""
+    print("full-size uneven batch", flush=True)
+    probs = wl.chain_batch(n_imp=512, Ls=(32, 48, 64, 96, 128), seed=3)
+    gpu = ctx.solve(probs)
+    assert all(g["status"] == 0 for g in gpu)
+    idx = [max((i for i, p in enumerate(probs) if p["L"] == L), key=lambda i: gpu[i]["accepts"])
+           for L in (32, 48, 64, 96, 128)]
+    ref = oracle.run([probs[i] for i in idx], n_threads=5)
+    _compare_runs([gpu[i] for i in idx], ref, [probs[i] for i in idx])
+
+
+def test_full_size_slab_sampled(ctx):
+    """The 41 x 41 slab's 1281 sites at L = 80, 1000 + 10000 sweeps (window
+    kernel, the slab benchmark's launch); the site with the most accepted
+    flips and the central one are recomputed by the oracle."""
+    print("full-size slab", flush=True)
+    probs = wl.slab_41x41()
+    gpu = ctx.solve(probs)
+    assert all(g["status"] == 0 for g in gpu)
+    idx = sorted({int(np.argmax([g["accepts"] for g in gpu])), len(probs) // 2})
+    ref = oracle.run([probs[i] for i in idx], n_threads=2)
+    _compare_runs([gpu[i] for i in idx], ref, [probs[i] for i in idx])
+
+
 def test_empty_batch(ctx):
     from paper_1006_2716_amd import hfqmc
     print("empty batch", flush=True)
