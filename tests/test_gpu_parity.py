@@ -235,6 +235,21 @@ def test_full_size_slab_sampled(ctx):
     _compare_runs([gpu[i] for i in idx], ref, [probs[i] for i in idx])
 
 
+def test_full_size_L160_sampled(ctx):
+    """128 requests of the serving generator at L = 160 as one batch, 200 +
+    2000 sweeps (device-memory window kernel, the long-grid benchmark's
+    launch); the impurity with the most accepted flips is recomputed by the
+    oracle."""
+    print("full-size L=160 batch", flush=True)
+    sites, _, weiss = wl.serving_requests(n_sites=512, Ls=(160,), weights=(1,), seed=4)
+    probs = [dict(L=160, beta=s["beta"], U=s["U"], weiss=weiss(s, 0), n_warmup=200, n_measure=2000,
+                  recompute_every=50, n_bins=32, seed=s["seed"], site=s["site"]) for s in sites[:128]]
+    gpu = ctx.solve(probs)
+    assert all(g["status"] == 0 for g in gpu)
+    i = int(np.argmax([g["accepts"] for g in gpu]))
+    _compare_runs([gpu[i]], oracle.run([probs[i]]), [probs[i]])
+
+
 def test_empty_batch(ctx):
     from paper_1006_2716_amd import hfqmc
     print("empty batch", flush=True)
